@@ -1,0 +1,244 @@
+"""FP64 CPU oracle of the finite-volume RHS / TVD-RK3 path (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It loads ``oracle/liboracle.so`` (plain
+C, built by ``oracle/Makefile``) and shares no code with the HIP library.
+
+Every array is numpy float64 in structure-of-arrays layout
+``[ncomp, nz, ny, nx]``.  Component order follows the paper's state vectors:
+single phase ``U = (rho, rho u, rho v, rho w, E)``, ``W = (rho, u, v, w, p)``;
+five-equation model ``U = (a1 rho1, a2 rho2, rho u, rho v, rho w, E, a1)``,
+``W = (a1 rho1, a2 rho2, u, v, w, p, a1)`` (Sec. 2.1 and 2.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EULER, NS, DIM = 0, 1, 2
+PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build() -> None:
+    """Compile liboracle.so with the oracle's own Makefile."""
+    subprocess.run(["make", "-s", "-C", _HERE, "-B", "liboracle.so"], check=True)
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 6),
+        ("positivity", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("gamma1", ctypes.c_double), ("pinf1", ctypes.c_double),
+        ("gamma2", ctypes.c_double), ("pinf2", ctypes.c_double),
+        ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Config:
+    """Problem description (grid, model, boundary conditions, material)."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float = 1.0
+    dy: float = 1.0
+    dz: float = 1.0
+    model: int = EULER
+    bc: tuple = (PERIODIC,) * 6
+    gamma1: float = 1.4
+    pinf1: float = 0.0
+    gamma2: float = 1.4
+    pinf2: float = 0.0
+    mu: float = 0.0
+    prandtl: float = 0.72
+    positivity: int = -1          # -1: on for the five-equation model, off otherwise
+    eps_rho: float = 1e-12        # FP64 tolerances of Sec. 3.3
+    eps_rhoc2: float = 1e-10
+    eps_alpha: float = 1e-12
+    weno_eps: float = 1e-40
+
+    @property
+    def ncomp(self) -> int:
+        return 7 if self.model == DIM else 5
+
+    @property
+    def shape(self):
+        return (self.ncomp, self.nz, self.ny, self.nx)
+
+    def c_struct(self) -> _Cfg:
+        c = _Cfg()
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.model = self.model
+        for i, b in enumerate(self.bc):
+            c.bc[i] = int(b)
+        pos = self.positivity
+        if pos < 0:
+            pos = 1 if self.model == DIM else 0
+        c.positivity = pos
+        c.dx, c.dy, c.dz = self.dx, self.dy, self.dz
+        c.gamma1, c.pinf1, c.gamma2, c.pinf2 = self.gamma1, self.pinf1, self.gamma2, self.pinf2
+        c.mu, c.prandtl = self.mu, self.prandtl
+        c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
+        c.weno_eps = self.weno_eps
+        return c
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        cp = ctypes.POINTER(_Cfg)
+        L.orc_ncomp.argtypes = [cp]
+        L.orc_prim_to_cons.argtypes = [cp, dp, dp]
+        L.orc_cons_to_prim.argtypes = [cp, dp, dp]
+        L.orc_weno5z.argtypes = [ctypes.c_double] * 6
+        L.orc_weno5z.restype = ctypes.c_double
+        L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double]
+        L.orc_rk3_stage.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double]
+        L.orc_dt.argtypes = [cp, dp, ctypes.c_double]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_advance.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_advance.restype = ctypes.c_double
+        L.orc_face_count.argtypes = [cp, ctypes.c_int]
+        L.orc_face_count.restype = ctypes.c_long
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _arr(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def prim_to_cons(cfg: Config, W) -> np.ndarray:
+    W = _arr(W, cfg.shape)
+    U = np.empty_like(W)
+    c = cfg.c_struct()
+    lib().orc_prim_to_cons(ctypes.byref(c), _dp(W), _dp(U))
+    return U
+
+
+def cons_to_prim(cfg: Config, U) -> np.ndarray:
+    U = _arr(U, cfg.shape)
+    W = np.empty_like(U)
+    c = cfg.c_struct()
+    lib().orc_cons_to_prim(ctypes.byref(c), _dp(U), _dp(W))
+    return W
+
+
+def weno5z(a, b, c, d, e, eps=1e-40) -> float:
+    return lib().orc_weno5z(a, b, c, d, e, eps)
+
+
+def hllc(cfg: Config, d: int, WL, WR):
+    """HLLC flux (global frame) and upwinded normal velocity at a face normal to d."""
+    WL = _arr(WL)
+    WR = _arr(WR)
+    F = np.empty(cfg.ncomp)
+    uh = np.zeros(1)
+    c = cfg.c_struct()
+    lib().orc_hllc(ctypes.byref(c), d, _dp(WL), _dp(WR), _dp(F), _dp(uh))
+    return F, float(uh[0])
+
+
+def face_counts(cfg: Config):
+    c = cfg.c_struct()
+    return [lib().orc_face_count(ctypes.byref(c), d) for d in range(3)]
+
+
+def rhs(cfg: Config, U, dt: float = 0.0, return_flags: bool = False):
+    """R_NSE(U) (Eq. FVD + DIM source).  dt is used only by the flux limiter."""
+    U = _arr(U, cfg.shape)
+    R = np.empty_like(U)
+    c = cfg.c_struct()
+    flags = None
+    fptr = None
+    if return_flags:
+        flags = np.zeros(sum(face_counts(cfg)), dtype=np.uint8)
+        fptr = flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    lib().orc_rhs(ctypes.byref(c), _dp(U), _dp(R), float(dt), fptr)
+    if return_flags:
+        out = []
+        off = 0
+        for d, nf in enumerate(face_counts(cfg)):
+            shp = [cfg.nz, cfg.ny, cfg.nx]
+            shp[2 - d] += 1
+            out.append(flags[off:off + nf].reshape(shp))
+            off += nf
+        return R, out
+    return R
+
+
+def rhs_cells(cfg: Config, U, cells, dt: float = 0.0) -> np.ndarray:
+    """R at the given flat cell indices, shape [ncomp, len(cells)]."""
+    U = _arr(U, cfg.shape)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty((cfg.ncomp, len(cells)))
+    c = cfg.c_struct()
+    lib().orc_rhs_cells(ctypes.byref(c), _dp(U), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        len(cells), _dp(out), float(dt))
+    return out
+
+
+def rk3_stage(cfg: Config, stage: int, Un, Uk, dt: float) -> np.ndarray:
+    Un = _arr(Un, cfg.shape)
+    Uk = _arr(Uk, cfg.shape)
+    out = np.empty_like(Un)
+    c = cfg.c_struct()
+    lib().orc_rk3_stage(ctypes.byref(c), stage, _dp(Un), _dp(Uk), _dp(out), float(dt))
+    return out
+
+
+def rk3_step(cfg: Config, U, dt: float) -> np.ndarray:
+    U1 = rk3_stage(cfg, 1, U, U, dt)
+    U2 = rk3_stage(cfg, 2, U, U1, dt)
+    return rk3_stage(cfg, 3, U, U2, dt)
+
+
+def compute_dt(cfg: Config, U, cfl: float) -> float:
+    U = _arr(U, cfg.shape)
+    c = cfg.c_struct()
+    return lib().orc_dt(ctypes.byref(c), _dp(U), float(cfl))
+
+
+def advance(cfg: Config, U, nsteps: int, dt: float = 0.0, cfl: float = 0.5):
+    """Advance nsteps (fixed dt if dt > 0, else CFL).  Returns (U, t)."""
+    U = _arr(U, cfg.shape).copy()
+    c = cfg.c_struct()
+    t = lib().orc_advance(ctypes.byref(c), _dp(U), int(nsteps), float(dt), float(cfl))
+    return U, t
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
