@@ -1,0 +1,205 @@
+"""Benchmark of the fused finite-volume TVD-RK3 stage on one MI355X.
+
+Workload (default): compressible Navier-Stokes Taylor-Green vortex, Ma 0.1,
+Re 1600, Pr 0.72, constant viscosity, periodic 256^3, FP64, seeded +-1e-3
+velocity noise, WENO5-Z + HLLC + 4th-order viscous fluxes, TVD-RK3 at CFL 0.5.
+One timed "step" = one CFL time-step reduction + the three fused stage
+kernels (the whole hot path).  Inputs are generated on the device and
+resident in HBM before timing starts.
+
+Prints one JSON line.  ``value`` is cell-updates per second counted per RK
+stage (cells x 3 x steps / time).  ``roofline`` reports the stage kernel:
+its algorithmic FP64 operations per cell (counted from the scheme's formulas,
+see FLOPS_PER_CELL) times cells, over its mean duration measured with HIP
+events on the launch stream, against the MI355X FP64 vector peak; the HBM
+view (algorithmic bytes over the same duration) is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+
+# Algorithmic floating-point operations per cell per stage (+ - * / sqrt min
+# max abs each count 1), from the formulas of the scheme:
+#   WENO5-Z pair (both face values of a cell, one component, one direction): 95
+#   HLLC face: 91;  viscous face: 80;  cell-centred derivatives: 9 x 5;
+#   U -> W: 13 (+1 for T = p/rho);  divergence: 9 per component;  Shu-Osher combine: 5 per component.
+def flops_per_cell(model: int) -> int:
+    nc = 7 if model == 2 else 5
+    weno = 95 * nc * 3
+    hllc = 91 * 3 + (2 * 3 * 3 if model == 2 else 0)
+    visc = (80 * 3 + 45) if model == 1 else 0
+    conv = 13 + (1 if model == 1 else 0) + (10 if model == 2 else 0)
+    div = 9 * nc + (7 if model == 2 else 0)
+    rk = 5 * nc
+    return weno + hllc + visc + conv + div + rk
+
+
+def bytes_per_cell(nc: int, es: int, stage: int) -> int:
+    # stage 1 reads U^n and writes U^(1); stages 2-3 read U^n, U^(k) and write one array
+    return (2 if stage == 1 else 3) * nc * es
+
+
+def run_oracle_baseline(case_name: str) -> dict:
+    """The FP64 oracle timed on this host on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    from paper_2402_05193_amd import workloads as WL
+    n = 64
+    case = WL.taylor_green(n, viscous=True)
+    cfg = O.Config(**case.cfg_kwargs())
+    U = O.prim_to_cons(cfg, case.W)
+    dt = O.compute_dt(cfg, U, 0.5)
+    threads = O.max_threads()
+    t0 = time.perf_counter()
+    O.rk3_step(cfg, U, dt)
+    el = time.perf_counter() - t0
+    return {"value": n ** 3 * 3 / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one TVD-RK3 step (3 stages) of the NS Taylor-Green vortex at {n}^3 FP64 "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--model", choices=["ns", "euler", "dim"], default="ns")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one device copy of known size first (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2402_05193_amd import solver as S
+    from paper_2402_05193_amd import workloads as WL
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    model = {"ns": S.NS, "euler": S.EULER, "dim": S.DIM}[args.model]
+    dtype = S.F64 if args.dtype == "f64" else S.F32
+    if model == S.DIM:
+        case = WL.shock_bubble(2 * args.n if args.n < 256 else 256, args.n // 2 if args.n < 256 else 128,
+                               args.n // 2 if args.n < 256 else 128, with_field=False)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5)
+        rho2, u2, p2 = case.meta["post_shock"]
+        H = case.meta["H"]
+        params = [0.060, 0.090, H / 2, H / 2, 0.25 * H, WL.ALPHA_EPS, rho2, u2, p2, 1.2041, 101325.0, 0.1660]
+        case_id = S.CASE_SBI
+        workload = f"DIM shock-bubble Ma 1.22 air/He {cfg.nx}x{cfg.ny}x{cfg.nz}, limiters on, CFL 0.5"
+    else:
+        case = WL.taylor_green(args.n, viscous=(model == S.NS), with_field=False)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5)
+        params = [0.1, 1.0, 1e-3]
+        case_id = S.CASE_TGV
+        workload = (f"{'NS' if model == S.NS else 'Euler'} Taylor-Green vortex Ma 0.1"
+                    f"{' Re 1600 Pr 0.72' if model == S.NS else ''} periodic {args.n}^3, CFL 0.5")
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {nbytes} bytes read + {nbytes} bytes written", flush=True)
+        del a, b
+
+    U = S.empty_state(cfg, dev)
+    S.init_state(cfg, case_id, params, U, seed=2402)
+    A = torch.empty_like(U)
+    B = torch.empty_like(U)
+    ws = S.workspace(cfg, dev)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        S.compute_dt(cfg, U, dt_dev, ws)
+        for k, (Uk, Uo) in enumerate(((U, A), (A, B), (B, U))):
+            if events is not None:
+                events[k][0].record(stream)
+            S.rk3_stage(cfg, k + 1, U, Uk, Uo, 0.0, dt_dev)
+            if events is not None:
+                events[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(3)]
+           for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for s in range(args.steps):
+        step(evs[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    stage_ms = [[evs[s][k][0].elapsed_time(evs[s][k][1]) for s in range(args.steps)] for k in range(3)]
+    mean_stage_ms = sum(sum(x) for x in stage_ms) / (3 * args.steps)
+    ncell = cfg.ncells
+    value = ncell * 3 * args.steps / (ms_total * 1e-3)
+
+    es = 8 if dtype == S.F64 else 4
+    fpc = flops_per_cell(model)
+    flops_launch = fpc * ncell
+    achieved_tflops = flops_launch / (mean_stage_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if dtype == S.F64 else PEAK_FP32_TFLOPS
+    alg_bytes = sum(bytes_per_cell(cfg.ncomp, es, k + 1) for k in range(3)) / 3 * ncell
+    hbm_gbs = alg_bytes / (mean_stage_ms * 1e-3) / 1e9
+
+    finite = bool(torch.isfinite(U).all().item())
+    out = {
+        "metric": "cell-updates/s + % HBM roofline (RK3 stage, 256^3); batched p50/p99 latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded analytic initial condition generated on the device)",
+        "config": {"workload": workload, "cells": ncell, "ncomp": cfg.ncomp,
+                   "counted_per": "RK stage (3 per step); a step also runs the CFL reduction"},
+        "cell_steps_per_s": ncell * args.steps / (ms_total * 1e-3),
+        "stage_ms": {"mean": mean_stage_ms, "stage1": sum(stage_ms[0]) / args.steps,
+                     "stage2": sum(stage_ms[1]) / args.steps, "stage3": sum(stage_ms[2]) / args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / peak, "traffic": None,
+                     "kernel": "stage_kernel", "flops_per_cell": fpc},
+        "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell},
+        "wall_s": wall,
+        "state_finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_oracle_baseline(workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * fvrk3.h -- C ABI of the MI355X (gfx950) finite-volume RHS / TVD-RK3 library.
+ *
+ * The library evaluates the explicit finite-volume right-hand side of the
+ * compressible Navier-Stokes equations on a uniform Cartesian grid
+ * (arXiv:2402.05193, Sec. 3.2 Eq. (FVD)) and the third-order TVD Runge-Kutta
+ * update that consumes it (Sec. 3.4), for three models:
+ *   FV_EULER  single-phase inviscid       (Sec. 2.1, 3.5)
+ *   FV_NS     single-phase viscous        (Sec. 2.1 dissipative fluxes, Sec. 2.5)
+ *   FV_DIM    five-equation diffuse-interface two-phase model (Sec. 2.3, 3.6)
+ * with WENO5-Z reconstruction of primitive variables, the HLLC flux,
+ * 4th-order central viscous fluxes and, optionally (default for FV_DIM), the
+ * interpolation and flux positivity limiters of Sec. 3.3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays: device pointers to contiguous structure-of-arrays storage
+ *   [ncomp][nz][ny][nx], x fastest, element type cfg->dtype (double or
+ *   float), base address aligned to 16 bytes.  ncomp = 5 for FV_EULER/FV_NS
+ *   (U = rho, rho u, rho v, rho w, E; W = rho, u, v, w, p) and 7 for FV_DIM
+ *   (U = a1 rho1, a2 rho2, rho u, rho v, rho w, E, a1;
+ *    W = a1 rho1, a2 rho2, u, v, w, p, a1), the state vectors of Sec. 2.1 / 2.3.
+ *   Only interior cells are stored; boundary conditions are applied while
+ *   the kernels read neighbours.
+ * Ownership: the caller owns every buffer (states, workspace, outputs).  The
+ *   library allocates no device memory and keeps no device state.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   All calls are asynchronous and stream-ordered unless stated otherwise.
+ * Errors: every function returns FV_OK (0) or a negative fv_status.  Nothing
+ *   throws or aborts.  last_error() returns a thread-local message describing
+ *   the last failure of the calling thread.
+ * Re-entrancy: calls on different streams with disjoint buffers may run
+ *   concurrently.
+ */
+#ifndef FVRK3_H
+#define FVRK3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FV_ABI_VERSION 1
+
+enum fv_model { FV_EULER = 0, FV_NS = 1, FV_DIM = 2 };
+enum fv_dtype { FV_F64 = 0, FV_F32 = 1 };
+/* Boundary conditions by index mapping (Sec. 3.1): periodic wrap, zero
+ * gradient (first-order extrapolation), symmetry (mirror with the normal
+ * momentum negated; needs at least 3 cells along that axis).  Periodic must
+ * be set on both faces of an axis. */
+enum fv_bc { FV_PERIODIC = 0, FV_ZERO_GRADIENT = 1, FV_SYMMETRY = 2 };
+
+enum fv_status {
+    FV_OK = 0,
+    FV_EINVAL = -1,        /* invalid configuration or argument value      */
+    FV_ENULL = -2,         /* a required pointer is NULL                    */
+    FV_EALIGN = -3,        /* a device pointer is not 16-byte aligned       */
+    FV_EUNSUPPORTED = -4,  /* valid request that this build does not serve  */
+    FV_EHIP = -5,          /* a HIP runtime call or kernel launch failed    */
+    FV_EINADMISSIBLE = -6, /* check_state found an inadmissible cell        */
+    FV_ENONFINITE = -7     /* check_state found a NaN or Inf                */
+};
+
+/* Initial conditions served by init_state (parameters in `params`). */
+enum fv_case {
+    FV_CASE_UNIFORM = 0, /* params: the primitive state W (ncomp values)                    */
+    FV_CASE_TGV = 1,     /* Taylor-Green vortex on [0,2pi)^3 (cfg dx = 2pi/nx ...):
+                            params: Ma, rho0, noise amplitude (seeded +-noise on u, v, w)   */
+    FV_CASE_RIEMANN = 2, /* planar two-state problem: params: axis, x0 (fraction of the
+                            domain along axis), W_left (ncomp), W_right (ncomp)            */
+    FV_CASE_SBI = 3      /* shock-bubble: params: x_shock, x_c, y_c, z_c, radius, eps_alpha,
+                            W_postshock_air (rho, u, p), W_air (rho, p), rho_bubble;
+                            fluid 1 = bubble gas, fluid 2 = air; coordinates in metres     */
+};
+
+/* Problem description, passed by pointer to every call and copied into
+ * kernel arguments.  Zero tolerances select the per-precision defaults of
+ * Sec. 3.3 (FP64: eps_rho 1e-12, eps_rhoc2 1e-10, eps_alpha 1e-12;
+ * FP32: 1e-10, 1e-8, 1e-10); weno_eps 0 selects 1e-40 (FP64) / 1e-30 (FP32). */
+typedef struct fv_config {
+    int32_t abi_version; /* must be FV_ABI_VERSION                         */
+    int32_t nx, ny, nz;  /* interior cells, each >= 1                      */
+    int32_t model;       /* fv_model                                       */
+    int32_t dtype;       /* fv_dtype of every array                        */
+    int32_t bc[6];       /* fv_bc for x-, x+, y-, y+, z-, z+               */
+    int32_t positivity;  /* 1: limiters on, 0: off, -1: default (on for DIM) */
+    int32_t reserved;    /* must be 0                                      */
+    double dx, dy, dz;   /* uniform cell sizes, > 0                        */
+    double gamma1, pinf1;/* stiffened gas of fluid 1 (the only fluid for EULER/NS) */
+    double gamma2, pinf2;/* stiffened gas of fluid 2 (FV_DIM)              */
+    double mu;           /* constant dynamic viscosity (FV_NS), >= 0       */
+    double prandtl;      /* Prandtl number (FV_NS), > 0                    */
+    double eps_rho, eps_rhoc2, eps_alpha; /* limiter tolerances (0: default) */
+    double weno_eps;     /* WENO-Z epsilon (0: default)                    */
+    double cfl;          /* CFL number used by advance/compute_dt, > 0     */
+} fv_config;
+
+/* Result of check_state. */
+typedef struct fv_report {
+    int32_t status;         /* FV_OK, FV_ENONFINITE or FV_EINADMISSIBLE    */
+    int32_t bad_count_clamped; /* number of bad cells, saturated at 2^31-1  */
+    int64_t first_bad_cell; /* smallest flat index of a bad cell, -1 if none */
+} fv_report;
+
+/* Number of components for cfg->model (5 or 7), or a negative status. */
+int32_t fv_ncomp(const fv_config* cfg);
+
+/* Bytes of workspace needed by rk3_step / advance / compute_dt /
+ * check_state: two extra state arrays plus 256 bytes of device scalars. */
+int workspace_bytes(const fv_config* cfg, size_t* out);
+
+/* Analytic initial condition at cell centres, written as conservative
+ * variables U (compute_initial_condition of the paper's API, Sec. 6.1).
+ * Seeded noise uses splitmix64 keyed by (seed, 3*flat_index + component). */
+int init_state(const fv_config* cfg, int32_t case_id, const double* params, int32_t nparams,
+               uint64_t seed, void* U, void* stream);
+
+/* U = L_{W->U}(W) (Sec. 2.1/2.3 state vectors, Sec. 2.4 EOS). */
+int prim_to_cons(const fv_config* cfg, const void* W, void* U, void* stream);
+
+/* W = L_{U->W}(U). */
+int cons_to_prim(const fv_config* cfg, const void* U, void* W, void* stream);
+
+/* R = R_NSE(U), Eq. (FVD) plus the DIM volume-fraction source (Sec. 3.6).
+ * dt is used only by the flux limiter's admissibility test (ignored when the
+ * limiters are off).  U and R must not overlap. */
+int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
+
+/* One TVD-RK3 stage (Sec. 3.4), the benchmarked unit:
+ *   stage 1: Uout = Un + dt R(Un)                        (Uk must equal Un)
+ *   stage 2: Uout = 3/4 Un + 1/4 Uk + 1/4 dt R(Uk)
+ *   stage 3: Uout = 1/3 Un + 2/3 Uk + 2/3 dt R(Uk)
+ * dt_dev: optional device pointer to a double holding dt (then `dt` is
+ * ignored).  Uout must not overlap Uk; in stage 3 Uout may equal Un. */
+int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* Uk, void* Uout,
+              double dt, const double* dt_dev, void* stream);
+
+/* One full TVD-RK3 step in place: U <- I_RK3(U, R, dt).  ws: workspace of
+ * workspace_bytes(). */
+int rk3_step(const fv_config* cfg, void* U, double dt, void* ws, void* stream);
+
+/* dt = cfg->cfl * min(min_d dx_d / (|u_d| + c), (3/14) rho dx_min^2 / mu),
+ * written to the device double *dt_dev.  ws as for rk3_step. */
+int compute_dt(const fv_config* cfg, const void* U, double* dt_dev, void* ws, void* stream);
+
+/* Advance nsteps TVD-RK3 steps in place (the feedforward of the paper's API,
+ * Sec. 6.1).  dt > 0: fixed step; dt <= 0: CFL step recomputed on the device
+ * before every step.  t_inout (host, optional): incremented by the simulated
+ * time; the only host synchronisation of this call happens when it is given. */
+int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws,
+            void* stream);
+
+/* Vector-Jacobian product Ubar = (dR/dU)^T Rbar of the RHS.  Not built:
+ * returns FV_EUNSUPPORTED. */
+int rhs_adjoint(const fv_config* cfg, const void* U, const void* Rbar, void* Ubar, void* ws,
+                void* stream);
+
+/* Scan U for NaN/Inf and for cells outside the admissible set of Sec. 3.3
+ * (rho > 0 and rho c^2 > 0; DIM: 0 <= a1 <= 1, a_k rho_k > 0).  Synchronises
+ * the stream.  Returns the status also stored in out->status. */
+int check_state(const fv_config* cfg, const void* U, void* ws, fv_report* out, void* stream);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVRK3_H */

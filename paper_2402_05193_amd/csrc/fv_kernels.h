@@ -1,0 +1,79 @@
+// fv_kernels.h -- kernel argument blocks and launchers shared by the HIP
+// sources of the library (internal; the public interface is include/fvrk3.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fv_physics.h"
+
+#ifndef TILE_BX
+#define TILE_BX 16
+#endif
+#ifndef TILE_BY
+#define TILE_BY 16
+#endif
+
+namespace fv {
+
+// Arguments of the fused stage kernel (passed by value).
+template <typename Real>
+struct StageArgs {
+    const Real* Uk;      // state the RHS is evaluated on
+    const Real* Un;      // Runge-Kutta base state (stages 2, 3)
+    Real* out;           // R (mode 0) or the new stage state
+    const double* dt_dev;// device dt (or null: use dt)
+    double dt;
+    int mode;            // 0: R, 1..3: Shu-Osher stage
+    int nx, ny, nz;
+    long long ncell;     // component stride
+    int bc[6];
+    int tiles_x, tiles_y, zchunk, nchunks;
+    int positivity, ndim;
+    Material<Real> mat;
+    Tolerances<Real> tol;
+    Real weno_eps;
+    Real idx, idy, idz;
+    Real inv12dx, inv12dy, inv12dz, inv24dx, inv24dy, inv24dz;
+    Real mu, kappa;      // kappa = mu gamma / ((gamma-1) Pr)
+};
+
+struct LaunchGeom {
+    int nblocks;
+};
+
+template <typename Real>
+hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st);
+
+template <typename Real, int MODEL>
+size_t stage_lds_bytes();
+
+// Point-wise / reduction kernels (fv_aux.hip)
+struct AuxArgs {
+    int model, nx, ny, nz;
+    long long ncell;
+    double dx, dy, dz;
+    Material<double> matd;
+    Material<float> matf;
+};
+
+template <typename Real>
+hipError_t launch_prim_to_cons(const AuxArgs& a, const Real* W, Real* U, hipStream_t st);
+template <typename Real>
+hipError_t launch_cons_to_prim(const AuxArgs& a, const Real* U, Real* W, hipStream_t st);
+template <typename Real>
+hipError_t launch_init(const AuxArgs& a, int case_id, const double* params, int nparams, uint64_t seed, Real* U,
+                       hipStream_t st);
+// max over cells of the inverse CFL time step into *inv_max (uint64 bit pattern of a
+// non-negative double); then dt = cfl / max and *t_acc += dt (if t_acc).
+template <typename Real>
+hipError_t launch_dt(const AuxArgs& a, const Real* U, double mu, double cfl, unsigned long long* inv_max,
+                     double* dt_out, double* t_acc, hipStream_t st);
+// admissibility / finiteness scan; ws_words: [0] first bad index (int64, init INT64_MAX),
+// [1] count, [2] worst code
+template <typename Real>
+hipError_t launch_check(const AuxArgs& a, const Real* U, long long* ws_words, hipStream_t st);
+hipError_t launch_add_scalar(double* t_acc, const double* dt, hipStream_t st);
+
+}  // namespace fv

@@ -1,0 +1,411 @@
+// fv_physics.h -- point-wise device functions of the fused finite-volume stage
+// for gfx950: equation of state, primitive/conservative maps, WENO5-Z
+// reconstruction with smoothness indicators shared between the two faces of a
+// cell, the HLLC flux and the 4th-order central viscous flux.
+//
+// Notation follows arXiv:2402.05193: W primitive, U conservative (Sec. 2.1,
+// 2.3), stiffened gas and isobaric mixture closure (Sec. 2.4), WENO5-Z and
+// HLLC (Sec. 3.2 and the HLLC appendix), admissible sets (Sec. 3.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fv {
+
+enum { EULER = 0, NS = 1, DIM = 2 };
+enum { PERIODIC = 0, ZEROGRAD = 1, SYMMETRY = 2 };
+
+template <int MODEL>
+struct Layout;
+template <>
+struct Layout<EULER> {
+    static constexpr int NC = 5, V = 1, P = 4, A = -1;
+};
+template <>
+struct Layout<NS> {
+    static constexpr int NC = 5, V = 1, P = 4, A = -1;
+};
+template <>
+struct Layout<DIM> {
+    static constexpr int NC = 7, V = 2, P = 5, A = 6;
+};
+
+// Material constants in the form the device uses.
+//   single phase:  p = gm1 (E - ke) - gpinf,  rho e = iG p + PI,  rho c^2 = gamma (p + pinf)
+//   mixture:       Gamma(a1) = a1 iG1 + (1-a1) iG2,  Pi(a1) = a1 PI1 + (1-a1) PI2,
+//                  p = (rho e - Pi)/Gamma,  rho c^2 = ((Gamma+1) p + Pi)/Gamma
+template <typename Real>
+struct Material {
+    Real gamma, pinf, gm1, gpinf;  // fluid 1 (single phase)
+    Real iG1, PI1, iG2, PI2;       // 1/(gamma_k-1), gamma_k pinf_k/(gamma_k-1)
+};
+
+template <typename Real>
+struct Tolerances {
+    Real eps_rho, eps_rhoc2, eps_alpha;
+};
+
+// ---------------------------------------------------------------- EOS / maps
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real density(const Real* w)
+{
+    if constexpr (MODEL == DIM) return w[0] + w[1];
+    else return w[0];
+}
+
+// Gamma = 1/(gamma-1) and Pi = gamma pinf/(gamma-1) of the mixture at a1.
+template <typename Real>
+__device__ __forceinline__ void mixture(const Material<Real>& m, Real a1, Real& G, Real& Pi)
+{
+    const Real a2 = Real(1) - a1;
+    G = a1 * m.iG1 + a2 * m.iG2;
+    Pi = a1 * m.PI1 + a2 * m.PI2;
+}
+
+// rho e from the primitive state
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real rho_e(const Material<Real>& mat, const Real* w)
+{
+    constexpr int P = Layout<MODEL>::P;
+    if constexpr (MODEL == DIM) {
+        Real G, Pi;
+        mixture(mat, w[6], G, Pi);
+        return G * w[P] + Pi;
+    } else {
+        return (w[P] + mat.gpinf) / mat.gm1;
+    }
+}
+
+// rho c^2 (Sec. 3.3 helper variable)
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real rhoc2(const Material<Real>& mat, const Real* w)
+{
+    constexpr int P = Layout<MODEL>::P;
+    if constexpr (MODEL == DIM) {
+        Real G, Pi;
+        mixture(mat, w[6], G, Pi);
+        return ((G + Real(1)) * w[P] + Pi) / G;
+    } else {
+        return mat.gamma * (w[P] + mat.pinf);
+    }
+}
+
+// L_{U->W}
+template <typename Real, int MODEL>
+__device__ __forceinline__ void cons_to_prim(const Material<Real>& mat, const Real* u, Real* w)
+{
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P;
+    Real rho;
+    if constexpr (MODEL == DIM) {
+        w[0] = u[0];
+        w[1] = u[1];
+        w[6] = u[6];
+        rho = u[0] + u[1];
+    } else {
+        w[0] = u[0];
+        rho = u[0];
+    }
+    w[V] = u[V] / rho;
+    w[V + 1] = u[V + 1] / rho;
+    w[V + 2] = u[V + 2] / rho;
+    const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
+    const Real re = u[P] - ke;
+    if constexpr (MODEL == DIM) {
+        Real G, Pi;
+        mixture(mat, u[6], G, Pi);
+        w[P] = (re - Pi) / G;
+    } else {
+        w[P] = mat.gm1 * re - mat.gpinf;
+    }
+}
+
+// L_{W->U}
+template <typename Real, int MODEL>
+__device__ __forceinline__ void prim_to_cons(const Material<Real>& mat, const Real* w, Real* u)
+{
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P;
+    const Real rho = density<Real, MODEL>(w);
+    if constexpr (MODEL == DIM) {
+        u[0] = w[0];
+        u[1] = w[1];
+        u[6] = w[6];
+    } else {
+        u[0] = w[0];
+    }
+    u[V] = rho * w[V];
+    u[V + 1] = rho * w[V + 1];
+    u[V + 2] = rho * w[V + 2];
+    const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
+    u[P] = rho_e<Real, MODEL>(mat, w) + ke;
+}
+
+// ---------------------------------------------------------------- WENO5-Z
+// Both one-sided WENO5-Z values of cell i from v_{i-2..i+2} = a,b,c,d,e:
+//   vm = v^-_{i+1/2} (left-biased, stencils {i-2..i}, {i-1..i+1}, {i..i+2},
+//        linear weights 1/10, 6/10, 3/10),
+//   vp = v^+_{i-1/2} (the mirror image: same smoothness indicators in
+//        reverse order).
+// Weights alpha_k = d_k (1 + tau / (beta_k + eps)) with tau = |beta0 - beta2|
+// (WENO-Z, exponent 1).  The 1/(beta_k + eps) and the factors
+// g_k = 1 + tau/(beta_k + eps) are computed once for both sides.
+template <typename Real>
+__device__ __forceinline__ void weno5z_pair(Real a, Real b, Real c, Real d, Real e, Real eps, Real& vm,
+                                            Real& vp)
+{
+    const Real k13 = Real(13.0 / 12.0), q = Real(0.25);
+    const Real t0 = a - Real(2) * b + c;
+    const Real s0 = a - Real(4) * b + Real(3) * c;
+    const Real t1 = b - Real(2) * c + d;
+    const Real s1 = b - d;
+    const Real t2 = c - Real(2) * d + e;
+    const Real s2 = Real(3) * c - Real(4) * d + e;
+    const Real b0 = k13 * t0 * t0 + q * s0 * s0;
+    const Real b1 = k13 * t1 * t1 + q * s1 * s1;
+    const Real b2 = k13 * t2 * t2 + q * s2 * s2;
+    const Real tau = fabs(b0 - b2);
+    const Real g0 = Real(1) + tau / (b0 + eps);
+    const Real g1 = Real(1) + tau / (b1 + eps);
+    const Real g2 = Real(1) + tau / (b2 + eps);
+    // candidate values (times 6)
+    const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
+    const Real p1 = -b + Real(5) * c + Real(2) * d;
+    const Real p2 = Real(2) * c + Real(5) * d - e;
+    const Real r0 = Real(2) * e - Real(7) * d + Real(11) * c;
+    const Real r1 = -d + Real(5) * c + Real(2) * b;
+    const Real r2 = Real(2) * c + Real(5) * b - a;
+    // alpha scaled by 10: (1, 6, 3) g for vm and (3, 6, 1) g reversed for vp
+    const Real m0 = g0, m1 = Real(6) * g1, m2 = Real(3) * g2;
+    const Real n0 = g2, n2 = Real(3) * g0;
+    vm = (m0 * p0 + m1 * p1 + m2 * p2) / (Real(6) * (m0 + m1 + m2));
+    vp = (n0 * r0 + m1 * r1 + n2 * r2) / (Real(6) * (n0 + m1 + n2));
+}
+
+// ---------------------------------------------------------------- HLLC
+// Face normal to direction DIR.  wl, wr: primitive states.  F: flux F^c in
+// the global frame; uh: upwinded normal velocity u^HLLC.  Wave speeds:
+// Einfeldt with Roe-averaged u-bar and c-bar, s* after Batten.  sgn(0) = 0:
+// for s* == 0 both star-side fluxes are averaged.
+template <typename Real, int MODEL, int DIR>
+__device__ __forceinline__ void hllc_side(const Material<Real>& mat, const Real* w, Real rho, Real un, Real sK,
+                                          Real sw, Real sstar, Real* F, Real& uh)
+{
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P, NC = Layout<MODEL>::NC;
+    const Real p = w[P];
+    const Real r = Real(1) / (sK - sstar);
+    const Real fac = (sK - un) * r;          // (s^K - u^K)/(s^K - s*)
+    const Real q = un + sw * (fac - Real(1)); // flux of any advected density per unit density
+    const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
+    const Real E = rho_e<Real, MODEL>(mat, w) + ke;
+    if constexpr (MODEL == DIM) {
+        F[0] = w[0] * q;
+        F[1] = w[1] * q;
+        F[6] = w[6] * q;
+    } else {
+        F[0] = rho * q;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        if (m == DIR) continue;
+        F[V + m] = rho * w[V + m] * q;
+    }
+    // normal momentum: rho u^2 + p + sw (fac rho s* - rho u)
+    F[V + DIR] = rho * un * un + p + sw * (fac * rho * sstar - rho * un);
+    // energy: u (E + p) + sw (E* - E),
+    //   E* = fac (E + (s* - u)(rho s* + p/(s^K - u))) = fac (E + (s*-u) rho s*) + (s*-u) p r
+    const Real ds = sstar - un;
+    const Real Estar = fac * (E + ds * rho * sstar) + ds * p * r;
+    F[P] = un * (E + p) + sw * (Estar - E);
+    uh = q;
+    (void)NC;
+}
+
+template <typename Real, int MODEL, int DIR>
+__device__ __forceinline__ void hllc(const Material<Real>& mat, const Real* wl, const Real* wr, Real* F, Real& uh)
+{
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P, NC = Layout<MODEL>::NC;
+    const Real rhoL = density<Real, MODEL>(wl), rhoR = density<Real, MODEL>(wr);
+    const Real uL = wl[V + DIR], uR = wr[V + DIR];
+    const Real pL = wl[P], pR = wr[P];
+    const Real c2L = rhoc2<Real, MODEL>(mat, wl) / rhoL;
+    const Real c2R = rhoc2<Real, MODEL>(mat, wr) / rhoR;
+    const Real cL = sqrt(c2L), cR = sqrt(c2R);
+    const Real sqL = sqrt(rhoL), sqR = sqrt(rhoR);
+    const Real isum = Real(1) / (sqL + sqR);
+    const Real ubar = (sqL * uL + sqR * uR) * isum;
+    const Real du = uR - uL;
+    const Real cbar2 = (sqL * c2L + sqR * c2R) * isum + Real(0.5) * sqL * sqR * isum * isum * du * du;
+    const Real cbar = sqrt(cbar2);
+    const Real sL = fmin(ubar - cbar, uL - cL);
+    const Real sR = fmax(ubar + cbar, uR + cR);
+    const Real mL = rhoL * (sL - uL), mR = rhoR * (sR - uR);
+    const Real sstar = ((pR - pL) + (mL * uL - mR * uR)) / (mL - mR);
+    const Real sminus = fmin(Real(0), sL), splus = fmax(Real(0), sR);
+    // one side unless s* == 0 (sgn(0) = 0 averages both)
+    const bool left = !(sstar < Real(0));
+    Real Fa[NC];
+    Real uha;
+    if (left) hllc_side<Real, MODEL, DIR>(mat, wl, rhoL, uL, sL, sminus, sstar, Fa, uha);
+    else hllc_side<Real, MODEL, DIR>(mat, wr, rhoR, uR, sR, splus, sstar, Fa, uha);
+    if (sstar == Real(0)) {
+        Real Fb[NC];
+        Real uhb;
+        hllc_side<Real, MODEL, DIR>(mat, wr, rhoR, uR, sR, splus, sstar, Fb, uhb);
+#pragma unroll
+        for (int m = 0; m < NC; m++) Fa[m] = Real(0.5) * Fa[m] + Real(0.5) * Fb[m];
+        uha = Real(0.5) * uha + Real(0.5) * uhb;
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) F[m] = Fa[m];
+    uh = uha;
+}
+
+// ---------------------------------------------------------------- admissibility
+// 1 if the primitive state violates any loop of the interpolation limiter
+// (densities, volume fraction, rho c^2).
+template <typename Real, int MODEL>
+__device__ __forceinline__ bool inadmissible_w(const Material<Real>& mat, const Tolerances<Real>& tol,
+                                               const Real* w)
+{
+    bool bad;
+    if constexpr (MODEL == DIM) {
+        bad = (w[0] < tol.eps_rho) || (w[1] < tol.eps_rho) || (w[6] < tol.eps_alpha) ||
+              (w[6] > Real(1) - tol.eps_alpha);
+    } else {
+        bad = w[0] < tol.eps_rho;
+    }
+    return bad || (rhoc2<Real, MODEL>(mat, w) < tol.eps_rhoc2);
+}
+
+// Convective flux F^c of a primitive state in direction DIR.
+template <typename Real, int MODEL, int DIR>
+__device__ __forceinline__ void physical_flux(const Material<Real>& mat, const Real* w, Real* F)
+{
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P;
+    const Real rho = density<Real, MODEL>(w);
+    const Real un = w[V + DIR];
+    if constexpr (MODEL == DIM) {
+        F[0] = w[0] * un;
+        F[1] = w[1] * un;
+        F[6] = w[6] * un;
+    } else {
+        F[0] = rho * un;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; m++) F[V + m] = rho * un * w[V + m];
+    F[V + DIR] += w[P];
+    const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
+    F[P] = un * (rho_e<Real, MODEL>(mat, w) + ke + w[P]);
+}
+
+// Flux limiter test (Sec. 3.3 item 2): split forward-Euler states of the two
+// cells adjacent to the face, U_i - lam (F - F(U_i)) and U_{i+1} + lam (F -
+// F(U_{i+1})) with lam = 2 D dt/dx; the volume fraction uses its
+// quasi-conservative split with the u^HLLC source.  Returns true if either
+// state violates a loop's tolerance.
+template <typename Real, int MODEL, int DIR>
+__device__ __forceinline__ bool flux_limiter_trips(const Material<Real>& mat, const Tolerances<Real>& tol,
+                                                   const Real* wi, const Real* wj, const Real* F, Real uh,
+                                                   Real lam)
+{
+    constexpr int NC = Layout<MODEL>::NC;
+    bool bad = false;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        const Real* w = side == 0 ? wi : wj;
+        const Real sg = side == 0 ? -lam : lam;
+        Real u[NC], f[NC], us[NC], ws[NC];
+        prim_to_cons<Real, MODEL>(mat, w, u);
+        physical_flux<Real, MODEL, DIR>(mat, w, f);
+#pragma unroll
+        for (int m = 0; m < NC; m++) us[m] = u[m] + sg * (F[m] - f[m]);
+        if constexpr (MODEL == DIM) us[6] = u[6] + sg * (F[6] - u[6] * uh);
+        cons_to_prim<Real, MODEL>(mat, us, ws);
+        bad = bad || inadmissible_w<Real, MODEL>(mat, tol, ws);
+    }
+    return bad;
+}
+
+// ---------------------------------------------------------------- viscous
+// 4th-order central stencils:
+//   face normal derivative  ((q_{-1} - q_{+2}) + 27 (q_{+1} - q_0)) / (24 h)
+//   cell derivative         ((q_{-2} - q_{+2}) + 8 (q_{+1} - q_{-1})) / (12 h)
+//   face interpolation      (9 (q_0 + q_{+1}) - (q_{-1} + q_{+2})) / 16
+template <typename Real>
+__device__ __forceinline__ Real dface(Real a, Real b, Real c, Real d, Real inv24h)
+{
+    return ((a - d) + Real(27) * (c - b)) * inv24h;
+}
+template <typename Real>
+__device__ __forceinline__ Real dcell(Real m2, Real m1, Real p1, Real p2, Real inv12h)
+{
+    return ((m2 - p2) + Real(8) * (p1 - m1)) * inv12h;
+}
+template <typename Real>
+__device__ __forceinline__ Real ifc(Real a, Real b, Real c, Real d)
+{
+    return (Real(9) * (b + c) - (a + d)) * Real(0.0625);
+}
+
+// Dissipative flux F^d at a face normal to DIR.
+//  q[s][0..3] = (u, v, w, T) at the four cells -1, 0, +1, +2 across the face
+//  (T = p / rho; the gas constant cancels in kappa = mu gamma/((gamma-1) Pr)),
+//  dt1n[s] = d u_n / d x_t1, dt2n[s] = d u_n / d x_t2, dt1t1[s] = d u_t1 / d x_t1,
+//  dt2t2[s] = d u_t2 / d x_t2 at those cells (t1, t2 = the tangential axes in
+//  increasing order).  Output Fd[0..3] = (tau_n1, tau_n2, tau_n3, sum_i u_i tau_ni - q_n).
+template <typename Real, int DIR>
+__device__ __forceinline__ void viscous_flux(const Real (*q)[4], const Real* dt1n, const Real* dt2n,
+                                             const Real* dt1t1, const Real* dt2t2, Real mu, Real kappa,
+                                             Real inv24h, Real* Fd)
+{
+    constexpr int T1 = DIR == 0 ? 1 : 0;
+    constexpr int T2 = DIR == 2 ? 1 : 2;
+    Real dn[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) dn[c] = dface(q[0][c], q[1][c], q[2][c], q[3][c], inv24h);
+    Real vf[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) vf[c] = ifc(q[0][c], q[1][c], q[2][c], q[3][c]);
+    const Real g_t1n = ifc(dt1n[0], dt1n[1], dt1n[2], dt1n[3]);
+    const Real g_t2n = ifc(dt2n[0], dt2n[1], dt2n[2], dt2n[3]);
+    const Real g_t1t1 = ifc(dt1t1[0], dt1t1[1], dt1t1[2], dt1t1[3]);
+    const Real g_t2t2 = ifc(dt2t2[0], dt2t2[1], dt2t2[2], dt2t2[3]);
+    const Real div = dn[DIR] + g_t1t1 + g_t2t2;
+    Real tau[3];
+    tau[DIR] = mu * (Real(2) * dn[DIR]) - Real(2.0 / 3.0) * mu * div;
+    tau[T1] = mu * (g_t1n + dn[T1]);
+    tau[T2] = mu * (g_t2n + dn[T2]);
+    Fd[0] = tau[0];
+    Fd[1] = tau[1];
+    Fd[2] = tau[2];
+    Fd[3] = vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2] + kappa * dn[3];
+}
+
+// ---------------------------------------------------------------- boundary mapping
+// Index of the interior cell that supplies global index g along an axis of n
+// cells; toggles flip when a symmetry mirror was crossed.  Indices further out
+// than a mirror image (only reached by cells of ragged tiles that lie outside
+// the domain and are never written) are clamped.
+__device__ __forceinline__ int map_index(int g, int n, int lo, int hi, bool& flip)
+{
+    if (g < 0) {
+        if (lo == PERIODIC) {
+            int r = g % n;
+            return r < 0 ? r + n : r;
+        }
+        if (lo == ZEROGRAD) return 0;
+        flip = !flip;
+        int r = -g - 1;
+        return r < n ? r : n - 1;
+    }
+    if (g >= n) {
+        if (hi == PERIODIC) return g % n;
+        if (hi == ZEROGRAD) return n - 1;
+        flip = !flip;
+        int r = 2 * n - 1 - g;
+        return r >= 0 ? r : 0;
+    }
+    return g;
+}
+
+}  // namespace fv

@@ -1,0 +1,552 @@
+// fv_stage.hip -- the fused finite-volume RHS / TVD-RK3 stage kernel for gfx950.
+//
+// One kernel evaluates R_NSE (arXiv:2402.05193 Eq. (FVD), plus the volume
+// fraction source of Sec. 3.6) for a block of cells and applies one Shu-Osher
+// stage (Sec. 3.4) -- or writes R itself.  Face states and fluxes never
+// leave the chip.
+//
+// Work decomposition ("2.5-D z-march"):
+//  * a workgroup owns a BX x BY column tile and a chunk of z-planes and marches
+//    through them plane by plane;
+//  * each thread owns one (x, y) column and keeps a 6-plane register window of
+//    primitive states W(s-3..s+2) of that column: the z-direction
+//    reconstruction, Riemann solve and viscous flux run entirely in registers;
+//  * the current plane s, with a 3-cell ring of x/y halo cells mapped through
+//    the boundary conditions, is staged in LDS as primitives; x- and y-face
+//    work runs as flat task lists over LDS (cell reconstructions write both
+//    face states of a cell, sharing the smoothness indicators; face tasks
+//    solve the Riemann problem in place);
+//  * z-faces complete one plane behind, so cell s-2 is finalised at step s
+//    (combined with U^n and written once, coalesced, x fastest).
+#include <hip/hip_runtime.h>
+
+#include "fv_kernels.h"
+#include "fv_physics.h"
+
+namespace fv {
+
+template <typename Real>
+__device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* __restrict__ U, int gi, int gj,
+                                          int gk, Real* u, int nc, int V)
+{
+    bool fx = false, fy = false, fz = false;
+    const int i = map_index(gi, a.nx, a.bc[0], a.bc[1], fx);
+    const int j = map_index(gj, a.ny, a.bc[2], a.bc[3], fy);
+    const int k = map_index(gk, a.nz, a.bc[4], a.bc[5], fz);
+    const long long q = ((long long)k * a.ny + j) * a.nx + i;
+    for (int m = 0; m < nc; m++) u[m] = U[m * a.ncell + q];
+    if (fx) u[V] = -u[V];
+    if (fy) u[V + 1] = -u[V + 1];
+    if (fz) u[V + 2] = -u[V + 2];
+}
+
+// LDS geometry of one tile
+template <typename Real, int MODEL, int BX, int BY>
+struct Tile {
+    static constexpr int NC = Layout<MODEL>::NC;
+    static constexpr bool VISC = MODEL == NS;
+    static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho)
+    static constexpr int PX = BX + 6, PY = BY + 6;  // plane with 3-cell halo
+    static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
+    static constexpr int NFMAX = NFX > NFY ? NFX : NFY;
+    static constexpr int WP_SIZE = NW * PY * PX;
+    static constexpr int FB_SIZE = 2 * NC * NFMAX;       // face states (left, right), fluxes in place
+    static constexpr int UH_SIZE = MODEL == DIM ? NFMAX : 0;
+    static constexpr int RX = (BX + 4) * BY, RY = BX * (BY + 4);  // viscous cell regions
+    static constexpr int DZ_SIZE = VISC ? 2 * RX + 2 * RY : 0;    // d/dz of (u,w) on RX, (v,w) on RY
+    static constexpr int DT_SIZE = VISC ? 2 * (RX > RY ? RX : RY) : 0;  // in-plane tangential d/dx_t
+    static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : 0);
+    static constexpr size_t bytes()
+    {
+        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE);
+    }
+};
+
+template <typename Real, int MODEL, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
+{
+    using L = Layout<MODEL>;
+    using TL = Tile<Real, MODEL, BX, BY>;
+    constexpr int NC = L::NC, V = L::V, P = L::P;
+    constexpr bool VISC = TL::VISC;
+    constexpr int NW = TL::NW, PX = TL::PX, PY = TL::PY;
+    constexpr int NT = BX * BY;
+    constexpr int PLANE = PY * PX;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Real* Wp = reinterpret_cast<Real*>(smem_raw);
+    Real* FB = Wp + TL::WP_SIZE;
+    Real* UHB = FB + TL::FB_SIZE;
+    Real* DZX = UHB + TL::UH_SIZE;  // [2][BY][BX+4]   (u, w) d/dz, x-face region
+    Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
+    Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
+
+    const Material<Real> mat = a.mat;
+    const Tolerances<Real> tol = a.tol;
+    const Real weps = a.weno_eps;
+    const bool pos = a.positivity != 0;
+    const Real dt = a.dt_dev ? Real(*a.dt_dev) : Real(a.dt);
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    int b = blockIdx.x;
+    // blocks of one tile column are consecutive; consecutive tiles share an XCD's L2
+    const int chunk = b % a.nchunks;
+    b /= a.nchunks;
+    const int tileX = b % a.tiles_x;
+    const int tileY = b / a.tiles_x;
+    const int x0 = tileX * BX, y0 = tileY * BY;
+    const int z0 = chunk * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own_valid = gx < a.nx && gy < a.ny;
+
+    auto wp = [&](int f, int i, int j) -> Real& { return Wp[f * PLANE + (j + 3) * PX + (i + 3)]; };
+
+    // primitive state of an arbitrary (possibly outside) cell, plus T = p / rho
+    auto load_w = [&](int gi, int gj, int gk, Real* w) {
+        Real u[NC];
+        load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V);
+        cons_to_prim<Real, MODEL>(mat, u, w);
+        if constexpr (VISC) w[NC] = w[P] / w[0];
+    };
+
+    // register window W(s-3 .. s+2) of the own column
+    Real win[6][NW];
+    const int s_begin = VISC ? z0 - 2 : z0;
+#pragma unroll
+    for (int q = 0; q < 5; q++) load_w(gx, gy, s_begin - 3 + q, win[q]);
+
+    Real vminus[NC];       // v^-_{s-3/2} from the reconstruction of cell s-2
+    Real accA[NC], accB[NC];  // partial R of cells s-2 and s-1
+    Real srcA = 0, srcB = 0;  // DIM: sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
+    Real Dc[3][4];            // NS: (dw/dx, du/dx, dw/dy, dv/dy) at planes s-3, s-2, s-1
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        vminus[m] = 0;
+        accA[m] = 0;
+        accB[m] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) Dc[q][c] = 0;
+
+    const Real idx = a.idx, idy = a.idy, idz = a.idz;
+    const Real lamx = Real(2 * a.ndim) * dt * idx;
+    const Real lamy = Real(2 * a.ndim) * dt * idy;
+    const Real lamz = Real(2 * a.ndim) * dt * idz;
+
+    for (int s = s_begin; s <= z1 + 1; s++) {
+        load_w(gx, gy, s + 2, win[5]);
+        const bool xy = (s >= z0) && (s < z1);
+        const bool need_plane = xy || (VISC && s >= z0 - 2);
+        Real accC[NC];
+        Real srcC = 0;
+        Real Dnew[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < NC; m++) accC[m] = 0;
+
+        if (need_plane) {
+            __syncthreads();
+            // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
+#pragma unroll
+            for (int f = 0; f < NW; f++) wp(f, tx, ty) = win[3][f];
+            for (int h = tid; h < TL::NHALO; h += NT) {
+                int i, j;
+                if (h < 6 * BY) {
+                    j = h / 6;
+                    const int k = h % 6;
+                    i = k < 3 ? k - 3 : BX + k - 3;
+                } else if (h < 6 * BY + 6 * BX) {
+                    const int hh = h - 6 * BY;
+                    i = hh % BX;
+                    const int k = hh / BX;
+                    j = k < 3 ? k - 3 : BY + k - 3;
+                } else {
+                    const int hh = h - 6 * BY - 6 * BX;  // 2-deep corners (viscous cross terms)
+                    const int ci = hh & 3, cj = hh >> 2;
+                    i = ci < 2 ? ci - 2 : BX + ci - 2;
+                    j = cj < 2 ? cj - 2 : BY + cj - 2;
+                }
+                Real w[NW];
+                load_w(x0 + i, y0 + j, s, w);
+#pragma unroll
+                for (int f = 0; f < NW; f++) wp(f, i, j) = w[f];
+            }
+            if constexpr (VISC) {
+                if (xy) {
+                    // d/dz of the velocity at plane s: own column from the window
+                    const Real i12 = a.inv12dz;
+                    Real dz[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++)
+                        dz[c] = dcell(win[1][V + c], win[2][V + c], win[4][V + c], win[5][V + c], i12);
+                    DZX[0 * TL::RX + ty * (BX + 4) + tx + 2] = dz[0];
+                    DZX[1 * TL::RX + ty * (BX + 4) + tx + 2] = dz[2];
+                    DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
+                    DZY[1 * TL::RY + (ty + 2) * BX + tx] = dz[2];
+                    // halo columns of the viscous regions: from memory
+                    for (int h = tid; h < 4 * BY + 4 * BX; h += NT) {
+                        int i, j;
+                        if (h < 4 * BY) {
+                            j = h / 4;
+                            const int k = h % 4;
+                            i = k < 2 ? k - 2 : BX + k - 2;
+                        } else {
+                            const int hh = h - 4 * BY;
+                            i = hh % BX;
+                            const int k = hh / BX;
+                            j = k < 2 ? k - 2 : BY + k - 2;
+                        }
+                        Real w[4][NW];
+                        load_w(x0 + i, y0 + j, s - 2, w[0]);
+                        load_w(x0 + i, y0 + j, s - 1, w[1]);
+                        load_w(x0 + i, y0 + j, s + 1, w[2]);
+                        load_w(x0 + i, y0 + j, s + 2, w[3]);
+                        Real d[3];
+#pragma unroll
+                        for (int c = 0; c < 3; c++) d[c] = dcell(w[0][V + c], w[1][V + c], w[2][V + c], w[3][V + c], i12);
+                        if (h < 4 * BY) {
+                            DZX[0 * TL::RX + j * (BX + 4) + i + 2] = d[0];
+                            DZX[1 * TL::RX + j * (BX + 4) + i + 2] = d[2];
+                        } else {
+                            DZY[0 * TL::RY + (j + 2) * BX + i] = d[1];
+                            DZY[1 * TL::RY + (j + 2) * BX + i] = d[2];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            if (xy) {
+                // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
+                Real* FL = FB;
+                Real* FR = FB + NC * TL::NFX;
+                for (int t = tid; t < (BX + 2) * BY; t += NT) {
+                    const int j = t / (BX + 2), i = t % (BX + 2) - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
+                                    weps, vm, vp);
+                        if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
+                        if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                    }
+                }
+                if constexpr (VISC) {
+                    const Real i12 = a.inv12dy;
+                    for (int t = tid; t < TL::RX; t += NT) {
+                        const int j = t / (BX + 4), i = t % (BX + 4) - 2;
+                        DT[t] = dcell(wp(V, i, j - 2), wp(V, i, j - 1), wp(V, i, j + 1), wp(V, i, j + 2), i12);
+                        DT[TL::RX + t] =
+                            dcell(wp(V + 1, i, j - 2), wp(V + 1, i, j - 1), wp(V + 1, i, j + 1), wp(V + 1, i, j + 2), i12);
+                    }
+                }
+                __syncthreads();
+                // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
+                for (int t = tid; t < TL::NFX; t += NT) {
+                    const int j = t / (BX + 1), f = t % (BX + 1);
+                    Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wl[m] = FL[m * TL::NFX + t];
+                        wr[m] = FR[m * TL::NFX + t];
+                    }
+                    if (pos) {
+                        Real wi[NC], wj[NC];
+#pragma unroll
+                        for (int m = 0; m < NC; m++) {
+                            wi[m] = wp(m, f - 1, j);
+                            wj[m] = wp(m, f, j);
+                        }
+                        if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                            for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                        if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                            for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                        hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                        if (flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx))
+                            hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
+                    } else {
+                        hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                    }
+                    if constexpr (VISC) {
+                        Real q[4][4], d1[4], d2[4], d3[4], d4[4];
+#pragma unroll
+                        for (int c = 0; c < 4; c++) {
+                            const int i = f - 2 + c;
+                            q[c][0] = wp(V, i, j);
+                            q[c][1] = wp(V + 1, i, j);
+                            q[c][2] = wp(V + 2, i, j);
+                            q[c][3] = wp(NC, i, j);
+                            const int r = j * (BX + 4) + i + 2;
+                            d1[c] = DT[r];                 // du/dy
+                            d2[c] = DZX[r];                // du/dz
+                            d3[c] = DT[TL::RX + r];        // dv/dy
+                            d4[c] = DZX[TL::RX + r];       // dw/dz
+                        }
+                        Real Fd[4];
+                        viscous_flux<Real, 0>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dx, Fd);
+                        F[V] -= Fd[0];
+                        F[V + 1] -= Fd[1];
+                        F[V + 2] -= Fd[2];
+                        F[P] -= Fd[3];
+                    }
+#pragma unroll
+                    for (int m = 0; m < NC; m++) FL[m * TL::NFX + t] = F[m];
+                    if constexpr (MODEL == DIM) UHB[t] = uh;
+                }
+                __syncthreads();
+                // ---- P3: x divergence of the own cell
+                {
+                    const int fl = ty * (BX + 1) + tx;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) accC[m] = -(FL[m * TL::NFX + fl + 1] - FL[m * TL::NFX + fl]) * idx;
+                    if constexpr (MODEL == DIM) srcC = (UHB[fl + 1] - UHB[fl]) * idx;
+                }
+                __syncthreads();
+                // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
+                Real* GL = FB;
+                Real* GR = FB + NC * TL::NFY;
+                for (int t = tid; t < BX * (BY + 2); t += NT) {
+                    const int i = t % BX, j = t / BX - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
+                                    weps, vm, vp);
+                        if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
+                        if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                    }
+                }
+                if constexpr (VISC) {
+                    const Real i12 = a.inv12dx;
+                    for (int t = tid; t < TL::RY; t += NT) {
+                        const int i = t % BX, j = t / BX - 2;
+                        DT[t] = dcell(wp(V + 1, i - 2, j), wp(V + 1, i - 1, j), wp(V + 1, i + 1, j), wp(V + 1, i + 2, j), i12);
+                        DT[TL::RY + t] = dcell(wp(V, i - 2, j), wp(V, i - 1, j), wp(V, i + 1, j), wp(V, i + 2, j), i12);
+                    }
+                }
+                __syncthreads();
+                // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
+                for (int t = tid; t < TL::NFY; t += NT) {
+                    const int i = t % BX, f = t / BX;
+                    Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wl[m] = GL[m * TL::NFY + t];
+                        wr[m] = GR[m * TL::NFY + t];
+                    }
+                    if (pos) {
+                        Real wi[NC], wj[NC];
+#pragma unroll
+                        for (int m = 0; m < NC; m++) {
+                            wi[m] = wp(m, i, f - 1);
+                            wj[m] = wp(m, i, f);
+                        }
+                        if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                            for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                        if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                            for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                        hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                        if (flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy))
+                            hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
+                    } else {
+                        hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                    }
+                    if constexpr (VISC) {
+                        Real q[4][4], d1[4], d2[4], d3[4], d4[4];
+#pragma unroll
+                        for (int c = 0; c < 4; c++) {
+                            const int j = f - 2 + c;
+                            q[c][0] = wp(V, i, j);
+                            q[c][1] = wp(V + 1, i, j);
+                            q[c][2] = wp(V + 2, i, j);
+                            q[c][3] = wp(NC, i, j);
+                            const int r = (j + 2) * BX + i;
+                            d1[c] = DT[r];                 // dv/dx
+                            d2[c] = DZY[r];                // dv/dz
+                            d3[c] = DT[TL::RY + r];        // du/dx
+                            d4[c] = DZY[TL::RY + r];       // dw/dz
+                        }
+                        Real Fd[4];
+                        viscous_flux<Real, 1>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dy, Fd);
+                        F[V] -= Fd[0];
+                        F[V + 1] -= Fd[1];
+                        F[V + 2] -= Fd[2];
+                        F[P] -= Fd[3];
+                    }
+#pragma unroll
+                    for (int m = 0; m < NC; m++) GL[m * TL::NFY + t] = F[m];
+                    if constexpr (MODEL == DIM) UHB[t] = uh;
+                }
+                __syncthreads();
+                // ---- P6: y divergence of the own cell
+                {
+                    const int fl = ty * BX + tx;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) accC[m] -= (GL[m * TL::NFY + fl + BX] - GL[m * TL::NFY + fl]) * idy;
+                    if constexpr (MODEL == DIM) srcC += (UHB[fl + BX] - UHB[fl]) * idy;
+                }
+            }
+            if constexpr (VISC) {
+                // in-plane derivatives of the own column for the z faces
+                const Real i12x = a.inv12dx, i12y = a.inv12dy;
+                Dnew[0] = dcell(wp(V + 2, tx - 2, ty), wp(V + 2, tx - 1, ty), wp(V + 2, tx + 1, ty), wp(V + 2, tx + 2, ty), i12x);
+                Dnew[1] = dcell(wp(V, tx - 2, ty), wp(V, tx - 1, ty), wp(V, tx + 1, ty), wp(V, tx + 2, ty), i12x);
+                Dnew[2] = dcell(wp(V + 2, tx, ty - 2), wp(V + 2, tx, ty - 1), wp(V + 2, tx, ty + 1), wp(V + 2, tx, ty + 2), i12y);
+                Dnew[3] = dcell(wp(V + 1, tx, ty - 2), wp(V + 1, tx, ty - 1), wp(V + 1, tx, ty + 1), wp(V + 1, tx, ty + 2), i12y);
+            }
+        }
+
+        // ---- z work of the own column (registers only)
+        if (s >= z0) {
+            // reconstruction of cell s-1 from W(s-3 .. s+1) = win[0..4]
+            Real vm_new[NC], vp[NC];
+#pragma unroll
+            for (int m = 0; m < NC; m++)
+                weno5z_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], weps, vm_new[m], vp[m]);
+            if (s >= z0 + 1) {
+                // z face s-3/2 between cells s-2 (win[1]) and s-1 (win[2])
+                Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    wl[m] = vminus[m];
+                    wr[m] = vp[m];
+                }
+                if (pos) {
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = win[1][m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = win[2][m];
+                    hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1], win[2], F, uh, lamz))
+                        hllc<Real, MODEL, 2>(mat, win[1], win[2], F, uh);
+                } else {
+                    hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    Real q[4][4], d1[4], d2[4], d3[4], d4[4];
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        q[c][0] = win[c][V];
+                        q[c][1] = win[c][V + 1];
+                        q[c][2] = win[c][V + 2];
+                        q[c][3] = win[c][NC];
+                        const Real* D = c < 3 ? Dc[c] : Dnew;
+                        d1[c] = D[0];  // dw/dx
+                        d2[c] = D[2];  // dw/dy
+                        d3[c] = D[1];  // du/dx
+                        d4[c] = D[3];  // dv/dy
+                    }
+                    Real Fd[4];
+                    viscous_flux<Real, 2>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dz, Fd);
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    accA[m] -= F[m] * idz;
+                    accB[m] += F[m] * idz;
+                }
+                if constexpr (MODEL == DIM) {
+                    srcA -= uh * idz;
+                    srcB += uh * idz;
+                }
+            }
+            if (s >= z0 + 2 && own_valid) {
+                // finalise cell s-2
+                const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
+                Real r[NC];
+#pragma unroll
+                for (int m = 0; m < NC; m++) r[m] = accA[m];
+                if constexpr (MODEL == DIM) r[6] += win[1][6] * srcA;
+                if (a.mode == 0) {
+#pragma unroll
+                    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = r[m];
+                } else if (a.mode == 1) {
+#pragma unroll
+                    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = a.Uk[m * a.ncell + q] + dt * r[m];
+                } else if (a.mode == 2) {
+                    const Real c1 = Real(0.75), c2 = Real(0.25);
+#pragma unroll
+                    for (int m = 0; m < NC; m++)
+                        a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+                } else {
+                    const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
+#pragma unroll
+                    for (int m = 0; m < NC; m++)
+                        a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];
+        }
+        // rotate carries
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            accA[m] = accB[m];
+            accB[m] = accC[m];
+        }
+        srcA = srcB;
+        srcB = srcC;
+        if constexpr (VISC) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                Dc[0][c] = Dc[1][c];
+                Dc[1][c] = Dc[2][c];
+                Dc[2][c] = Dnew[c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; q++)
+#pragma unroll
+            for (int f = 0; f < NW; f++) win[q][f] = win[q + 1][f];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename Real, int MODEL, int BX, int BY>
+static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    using TL = Tile<Real, MODEL, BX, BY>;
+    const size_t lds = TL::bytes();
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, BX, BY>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, BX, BY>), dim3(g.nblocks), dim3(BX * BY), lds, st, args);
+    return hipGetLastError();
+}
+
+template <typename Real, int MODEL>
+size_t stage_lds_bytes()
+{
+    return Tile<Real, MODEL, TILE_BX, TILE_BY>::bytes();
+}
+
+template <typename Real>
+hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    switch (model) {
+    case EULER: return launch_tile<Real, EULER, TILE_BX, TILE_BY>(args, g, st);
+    case NS: return launch_tile<Real, NS, TILE_BX, TILE_BY>(args, g, st);
+    default: return launch_tile<Real, DIM, TILE_BX, TILE_BY>(args, g, st);
+    }
+}
+
+template hipError_t launch_stage<double>(int, const StageArgs<double>&, const LaunchGeom&, hipStream_t);
+template hipError_t launch_stage<float>(int, const StageArgs<float>&, const LaunchGeom&, hipStream_t);
+
+}  // namespace fv

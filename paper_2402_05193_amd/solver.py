@@ -1,0 +1,294 @@
+"""Thin Python binding of libfvrk3.so (include/fvrk3.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch supplies device memory (tensors) and the current HIP stream.  The
+library must be built (``python -m paper_2402_05193_amd.build``); importing
+this module without it raises immediately -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+EULER, NS, DIM = 0, 1, 2
+F64, F32 = 0, 1
+PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
+CASE_UNIFORM, CASE_TGV, CASE_RIEMANN, CASE_SBI = 0, 1, 2, 3
+ABI_VERSION = 1
+
+OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvrk3.so")
+
+EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rk3_stage",
+            "rk3_step", "compute_dt", "advance", "rhs_adjoint", "check_state", "last_error"]
+
+
+class FVError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 6),
+        ("positivity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("gamma1", ctypes.c_double), ("pinf1", ctypes.c_double),
+        ("gamma2", ctypes.c_double), ("pinf2", ctypes.c_double),
+        ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("bad_count_clamped", ctypes.c_int32),
+                ("first_bad_cell", ctypes.c_int64)]
+
+
+@dataclass
+class Config:
+    """Problem description mirrored into ``fv_config``."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float = 1.0
+    dy: float = 1.0
+    dz: float = 1.0
+    model: int = EULER
+    dtype: int = F64
+    bc: tuple = (PERIODIC,) * 6
+    gamma1: float = 1.4
+    pinf1: float = 0.0
+    gamma2: float = 1.4
+    pinf2: float = 0.0
+    mu: float = 0.0
+    prandtl: float = 0.72
+    positivity: int = -1
+    eps_rho: float = 0.0
+    eps_rhoc2: float = 0.0
+    eps_alpha: float = 0.0
+    weno_eps: float = 0.0
+    cfl: float = 0.5
+
+    @property
+    def ncomp(self) -> int:
+        return 7 if self.model == DIM else 5
+
+    @property
+    def shape(self):
+        return (self.ncomp, self.nz, self.ny, self.nx)
+
+    @property
+    def torch_dtype(self):
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c_struct(self) -> _Cfg:
+        c = _Cfg()
+        c.abi_version = ABI_VERSION
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.model, c.dtype = self.model, self.dtype
+        for i, b in enumerate(self.bc):
+            c.bc[i] = int(b)
+        c.positivity, c.reserved = self.positivity, 0
+        c.dx, c.dy, c.dz = self.dx, self.dy, self.dz
+        c.gamma1, c.pinf1, c.gamma2, c.pinf2 = self.gamma1, self.pinf1, self.gamma2, self.pinf2
+        c.mu, c.prandtl = self.mu, self.prandtl
+        c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
+        c.weno_eps, c.cfl = self.weno_eps, self.cfl
+        return c
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_05193_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        cp = ctypes.POINTER(_Cfg)
+        vp = ctypes.c_void_p
+        L.fv_ncomp.argtypes = [cp]
+        L.workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+        L.init_state.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                 ctypes.c_uint64, vp, vp]
+        L.prim_to_cons.argtypes = [cp, vp, vp, vp]
+        L.cons_to_prim.argtypes = [cp, vp, vp, vp]
+        L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
+        L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
+        L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
+        L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
+        L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
+        L.check_state.argtypes = [cp, vp, vp, ctypes.POINTER(Report), vp]
+        L.last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("last_error",):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise FVError(code, lib().last_error().decode())
+    return code
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _state(cfg: Config, t: torch.Tensor, name: str):
+    if t.dtype != cfg.torch_dtype or not t.is_contiguous() or t.numel() != cfg.ncomp * cfg.ncells:
+        raise ValueError(f"{name}: expected a contiguous {cfg.torch_dtype} tensor of {cfg.shape}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+
+
+# ------------------------------------------------------------------ API
+def ncomp(cfg: Config) -> int:
+    c = cfg.c_struct()
+    r = lib().fv_ncomp(ctypes.byref(c))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def workspace_bytes(cfg: Config) -> int:
+    c = cfg.c_struct()
+    out = ctypes.c_size_t(0)
+    _check(lib().workspace_bytes(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+def empty_state(cfg: Config, device="cuda") -> torch.Tensor:
+    return torch.empty(cfg.shape, dtype=cfg.torch_dtype, device=device)
+
+
+def workspace(cfg: Config, device="cuda") -> torch.Tensor:
+    return torch.empty(workspace_bytes(cfg), dtype=torch.uint8, device=device)
+
+
+def init_state(cfg: Config, case_id: int, params, U: torch.Tensor, seed: int = 0, stream=None):
+    _state(cfg, U, "U")
+    arr = (ctypes.c_double * max(1, len(params)))(*[float(p) for p in params])
+    c = cfg.c_struct()
+    _check(lib().init_state(ctypes.byref(c), int(case_id), arr, len(params), ctypes.c_uint64(seed & (2**64 - 1)),
+                            _ptr(U), _stream(stream)))
+    return U
+
+
+def prim_to_cons(cfg: Config, W: torch.Tensor, U: torch.Tensor, stream=None):
+    _state(cfg, W, "W")
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    _check(lib().prim_to_cons(ctypes.byref(c), _ptr(W), _ptr(U), _stream(stream)))
+    return U
+
+
+def cons_to_prim(cfg: Config, U: torch.Tensor, W: torch.Tensor, stream=None):
+    _state(cfg, U, "U")
+    _state(cfg, W, "W")
+    c = cfg.c_struct()
+    _check(lib().cons_to_prim(ctypes.byref(c), _ptr(U), _ptr(W), _stream(stream)))
+    return W
+
+
+def rhs(cfg: Config, U: torch.Tensor, R: torch.Tensor, dt: float = 0.0, stream=None):
+    _state(cfg, U, "U")
+    _state(cfg, R, "R")
+    c = cfg.c_struct()
+    _check(lib().rhs(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _stream(stream)))
+    return R
+
+
+def rk3_stage(cfg: Config, stage: int, Un, Uk, Uout, dt: float = 0.0, dt_dev: torch.Tensor | None = None,
+              stream=None):
+    for t, n in ((Un, "Un"), (Uk, "Uk"), (Uout, "Uout")):
+        _state(cfg, t, n)
+    c = cfg.c_struct()
+    _check(lib().rk3_stage(ctypes.byref(c), int(stage), _ptr(Un), _ptr(Uk), _ptr(Uout), float(dt), _ptr(dt_dev),
+                           _stream(stream)))
+    return Uout
+
+
+def rk3_step(cfg: Config, U: torch.Tensor, dt: float, ws: torch.Tensor, stream=None):
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    _check(lib().rk3_step(ctypes.byref(c), _ptr(U), float(dt), _ptr(ws), _stream(stream)))
+    return U
+
+
+def compute_dt(cfg: Config, U: torch.Tensor, dt_dev: torch.Tensor, ws: torch.Tensor, stream=None):
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    _check(lib().compute_dt(ctypes.byref(c), _ptr(U), _ptr(dt_dev), _ptr(ws), _stream(stream)))
+    return dt_dev
+
+
+def advance(cfg: Config, U: torch.Tensor, nsteps: int, dt: float, ws: torch.Tensor, t: float | None = None,
+            stream=None):
+    """Advance in place; returns the new time if ``t`` is given (one host sync), else None."""
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    tp = None
+    tv = None
+    if t is not None:
+        tv = ctypes.c_double(t)
+        tp = ctypes.byref(tv)
+    _check(lib().advance(ctypes.byref(c), _ptr(U), int(nsteps), float(dt), tp, _ptr(ws), _stream(stream)))
+    return tv.value if tv is not None else None
+
+
+def rhs_adjoint(cfg: Config, U, Rbar, Ubar, ws, stream=None):
+    c = cfg.c_struct()
+    _check(lib().rhs_adjoint(ctypes.byref(c), _ptr(U), _ptr(Rbar), _ptr(Ubar), _ptr(ws), _stream(stream)))
+
+
+def check_state(cfg: Config, U: torch.Tensor, ws: torch.Tensor, stream=None) -> Report:
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    rep = Report()
+    code = lib().check_state(ctypes.byref(c), _ptr(U), _ptr(ws), ctypes.byref(rep), _stream(stream))
+    if code not in (OK, EINADMISSIBLE, ENONFINITE):
+        _check(code)
+    return rep
+
+
+def last_error() -> str:
+    return lib().last_error().decode()
+
+
+def config_from_case(case, dtype: int = F64, **over) -> Config:
+    """Solver config for a workloads.Case."""
+    kw = case.cfg_kwargs()
+    kw.update(over)
+    return Config(dtype=dtype, **kw)

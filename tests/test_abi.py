@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every entry point of include/fvrk3.h;
+host-side validation returns the documented codes (no GPU needed: every case
+here fails before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fvrk3.h")
+
+S = pytest.importorskip("paper_2402_05193_amd.solver")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|const char\*|size_t)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("init_state", "rhs", "rk3_step", "advance", "rhs_adjoint", "rk3_stage", "prim_to_cons",
+                 "workspace_bytes", "check_state", "last_error", "compute_dt"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def cfg(**kw):
+    base = dict(nx=8, ny=8, nz=8, dx=0.1, dy=0.1, dz=0.1)
+    base.update(kw)
+    return S.Config(**base)
+
+
+def call_rhs(c, U=256, R=512, dt=0.0):
+    cs = c.c_struct()
+    return S.lib().rhs(ctypes.byref(cs), U, R, dt, None)
+
+
+def test_validation_codes():
+    assert call_rhs(cfg(nx=0)) == S.EINVAL
+    assert call_rhs(cfg(model=7)) == S.EINVAL
+    assert call_rhs(cfg(dtype=3)) == S.EINVAL
+    assert call_rhs(cfg(dx=-1.0)) == S.EINVAL
+    assert call_rhs(cfg(gamma1=1.0)) == S.EINVAL
+    assert call_rhs(cfg(bc=(S.PERIODIC, S.ZERO_GRADIENT) + (S.PERIODIC,) * 4)) == S.EINVAL
+    assert call_rhs(cfg(nx=2, bc=(S.SYMMETRY,) * 2 + (S.PERIODIC,) * 4)) == S.EINVAL
+    assert call_rhs(cfg(), U=None) == S.ENULL
+    assert call_rhs(cfg(), U=264) == S.EALIGN
+    assert call_rhs(cfg(), U=256, R=256) == S.EINVAL
+    assert call_rhs(cfg(), dt=float("nan")) == S.EINVAL
+    assert "dt" in S.last_error()
+    c = cfg().c_struct()
+    c.abi_version = 99
+    assert S.lib().rhs(ctypes.byref(c), 256, 512, 0.0, None) == S.EINVAL
+    assert "abi_version" in S.last_error()
+    assert S.lib().rhs(None, 256, 512, 0.0, None) == S.ENULL
+
+
+def test_stage_and_step_validation():
+    c = cfg().c_struct()
+    L = S.lib()
+    assert L.rk3_stage(ctypes.byref(c), 4, 256, 256, 512, 1e-3, None, None) == S.EINVAL
+    assert L.rk3_stage(ctypes.byref(c), 1, 256, 768, 512, 1e-3, None, None) == S.EINVAL  # stage 1 needs Uk == Un
+    assert L.rk3_stage(ctypes.byref(c), 2, 256, 512, 512, 1e-3, None, None) == S.EINVAL  # Uout aliases Uk
+    assert L.rk3_stage(ctypes.byref(c), 2, 256, 512, 768, 0.0, None, None) == S.EINVAL  # dt <= 0
+    assert L.rk3_step(ctypes.byref(c), 256, 1e-3, None, None) == S.ENULL
+    assert L.advance(ctypes.byref(c), 256, -1, 1e-3, None, 512, None) == S.EINVAL
+    c2 = cfg(cfl=0.0).c_struct()
+    assert L.advance(ctypes.byref(c2), 256, 3, 0.0, None, 512, None) == S.EINVAL
+    assert L.rhs_adjoint(ctypes.byref(c), 256, 512, 768, 1024, None) == S.EUNSUPPORTED
+    assert L.init_state(ctypes.byref(c), 99, None, 0, 0, 256, None) == S.EINVAL
+    p = (ctypes.c_double * 2)(0.1, 1.0)
+    assert L.init_state(ctypes.byref(c), S.CASE_TGV, p, 2, 0, 256, None) == S.EINVAL  # too few params
+
+
+def test_workspace_and_ncomp():
+    c = cfg(nx=10, ny=3, nz=2)
+    state = 8 * 5 * 60
+    pad = (state + 255) // 256 * 256
+    assert S.workspace_bytes(c) == 2 * pad + 256
+    assert S.ncomp(c) == 5
+    assert S.ncomp(cfg(model=S.DIM)) == 7
+    assert S.workspace_bytes(cfg(dtype=S.F32)) == 2 * ((4 * 5 * 512 + 255) // 256 * 256) + 256

@@ -1,0 +1,304 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides receive the same conservative state: the seeded primitive field of
+paper_2402_05193_amd.workloads converted by the oracle.  Bar (FP64): per
+component, max|R_gpu - R_oracle| / max|R_oracle| <= 1e-12 for one RHS, and
+max|U_gpu - U_oracle| / max|U_oracle| <= 1e-10 after 100 TVD-RK3 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2402_05193_amd import solver as S
+from paper_2402_05193_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+RHS_TOL = 1e-12
+STEP_TOL = 1e-10
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def comp_rel(gpu, ref):
+    """Per-component max abs difference over max abs reference (reference-scale floor for zero components)."""
+    nc = ref.shape[0]
+    g = gpu.reshape(nc, -1)
+    r = ref.reshape(nc, -1)
+    scale_all = np.abs(r).max()
+    out = []
+    for m in range(nc):
+        s = np.abs(r[m]).max()
+        if s < 1e-300:
+            s = scale_all
+        out.append(np.abs(g[m] - r[m]).max() / s)
+    return np.array(out)
+
+
+def oracle_cfg(case, **kw):
+    d = case.cfg_kwargs()
+    d.update(kw)
+    return O.Config(**d)
+
+
+def solver_cfg(case, dtype=S.F64, **kw):
+    return S.config_from_case(case, dtype=dtype, **kw)
+
+
+MIXED_BC = (WL.PERIODIC, WL.PERIODIC, WL.ZERO_GRADIENT, WL.ZERO_GRADIENT, WL.SYMMETRY, WL.SYMMETRY)
+
+
+def cases():
+    return {
+        "euler_tgv32": WL.taylor_green(32),
+        "euler_ragged": WL.smooth_random(13, 11, 9, model=WL.EULER, seed=21, bc=MIXED_BC),
+        "euler_line": WL.gauss_wave(64, axis=0),
+        "euler_plane": WL.smooth_random(20, 17, 1, model=WL.EULER, seed=4),
+        "ns_tgv32": WL.taylor_green(32, viscous=True),
+        "ns_ragged": WL.smooth_random(19, 13, 10, model=WL.NS, seed=22, bc=MIXED_BC, mu=0.02, prandtl=0.7),
+        "dim_smooth": WL.smooth_random(12, 10, 9, model=WL.DIM, seed=23, gamma1=1.66, gamma2=1.4),
+        "dim_ragged": WL.smooth_random(17, 9, 7, model=WL.DIM, seed=24, bc=MIXED_BC, gamma1=6.12, pinf1=3.43,
+                                       gamma2=1.4),
+        "dim_sbi": WL.shock_bubble(48, 24, 24),
+    }
+
+
+@pytest.fixture(scope="module")
+def all_cases():
+    return cases()
+
+
+@pytest.mark.parametrize("name", list(cases().keys()))
+def test_rhs_parity(all_cases, name):
+    case = all_cases[name]
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    dt = 0.3 * O.compute_dt(oc, U, 1.0)
+    print(f"[parity] rhs {name} shape={U.shape} dt={dt:.3e}", flush=True)
+    Ro = O.rhs(oc, U, dt=dt)
+    sc = solver_cfg(case)
+    Ud = dev(U)
+    Rd = torch.empty_like(Ud)
+    S.rhs(sc, Ud, Rd, dt=dt)
+    err = comp_rel(host(Rd), Ro)
+    print(f"[parity] rhs {name} rel err per component {err}", flush=True)
+    assert np.all(err <= RHS_TOL), err
+
+
+def test_prim_to_cons_parity(all_cases):
+    for name, case in all_cases.items():
+        oc = oracle_cfg(case)
+        sc = solver_cfg(case)
+        Uo = O.prim_to_cons(oc, case.W)
+        Ud = S.prim_to_cons(sc, dev(case.W), S.empty_state(sc))
+        assert np.all(comp_rel(host(Ud), Uo) <= 1e-15), name
+        Wd = S.cons_to_prim(sc, dev(Uo), S.empty_state(sc))
+        assert np.all(comp_rel(host(Wd), case.W) <= 1e-14), name
+
+
+def test_init_state_tgv_matches_generator():
+    case = WL.taylor_green(24, seed=2402)
+    sc = solver_cfg(case)
+    Ud = S.init_state(sc, S.CASE_TGV, [0.1, 1.0, 1e-3], S.empty_state(sc), seed=2402)
+    Uo = O.prim_to_cons(oracle_cfg(case), case.W)
+    assert np.all(comp_rel(host(Ud), Uo) <= 1e-14)
+
+
+def test_init_state_sbi_matches_generator():
+    case = WL.shock_bubble(32, 16, 16)
+    sc = solver_cfg(case)
+    rho2, u2, p2 = case.meta["post_shock"]
+    H = case.meta["H"]
+    params = [0.060, 0.090, H / 2, H / 2, 0.25 * H, WL.ALPHA_EPS, rho2, u2, p2, 1.2041, 101325.0, 0.1660]
+    Ud = S.init_state(sc, S.CASE_SBI, params, S.empty_state(sc))
+    Uo = O.prim_to_cons(oracle_cfg(case), case.W)
+    assert np.all(comp_rel(host(Ud), Uo) <= 1e-14)
+
+
+def test_uniform_state_exactly_preserved():
+    for model, state, extra in [(WL.EULER, (1.3, 0.3, -0.2, 0.1, 2.0), {}),
+                                (WL.NS, (1.3, 0.3, -0.2, 0.1, 2.0), dict(mu=0.01)),
+                                (WL.DIM, (0.4, 0.35, 0.3, -0.2, 0.1, 2.0, 0.45), dict(gamma1=1.66))]:
+        for bc in (WL.PERIODIC, WL.ZERO_GRADIENT):
+            case = WL.uniform(23, 18, 13, model=model, state=state, bc=(bc,) * 6, h=(0.1, 0.2, 0.3), **extra)
+            sc = solver_cfg(case)
+            U = dev(O.prim_to_cons(oracle_cfg(case), case.W))
+            R = torch.empty_like(U)
+            S.rhs(sc, U, R, dt=1e-3)
+            assert int(torch.count_nonzero(R)) == 0, (model, bc)
+
+
+def test_conservation_on_gpu():
+    for model, extra in [(WL.EULER, {}), (WL.NS, dict(mu=0.01)), (WL.DIM, dict(gamma1=1.66))]:
+        case = WL.smooth_random(37, 29, 21, model=model, seed=31, **extra)
+        sc = solver_cfg(case)
+        U = dev(O.prim_to_cons(oracle_cfg(case), case.W))
+        R = torch.empty_like(U)
+        S.rhs(sc, U, R, dt=1e-4)
+        Rh = host(R).reshape(sc.ncomp, -1)
+        for m in range(6 if model == WL.DIM else 5):
+            assert abs(Rh[m].sum()) <= 1e-13 * np.abs(Rh[m]).sum(), (model, m)
+
+
+def test_mirror_symmetry_on_gpu():
+    case = WL.smooth_random(21, 18, 15, model=WL.NS, seed=5, bc=(WL.ZERO_GRADIENT,) * 6, mu=0.01)
+    sc = solver_cfg(case)
+    U = O.prim_to_cons(oracle_cfg(case), case.W)
+    R = host(S.rhs(sc, dev(U), S.empty_state(sc)))
+    for axis in range(3):
+        Um = np.flip(U, axis=3 - axis).copy()
+        Um[1 + axis] *= -1
+        Rm = host(S.rhs(sc, dev(Um), S.empty_state(sc)))
+        ref = np.flip(R, axis=3 - axis).copy()
+        ref[1 + axis] *= -1
+        assert np.all(comp_rel(Rm, ref) <= 1e-13), axis
+
+
+def test_determinism():
+    case = WL.shock_bubble(40, 20, 20)
+    sc = solver_cfg(case)
+    U = dev(O.prim_to_cons(oracle_cfg(case), case.W))
+    R1 = S.rhs(sc, U, torch.empty_like(U), dt=1e-7)
+    R2 = S.rhs(sc, U, torch.empty_like(U), dt=1e-7)
+    assert torch.equal(R1, R2)
+
+
+@pytest.mark.parametrize("name", ["euler_tgv32", "ns_ragged", "dim_smooth"])
+def test_rk3_step_parity(all_cases, name):
+    case = all_cases[name]
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    dt = 0.5 * O.compute_dt(oc, U, 1.0)
+    sc = solver_cfg(case)
+    Ud = dev(U)
+    # stages one by one through rk3_stage, and the whole step through rk3_step
+    A = torch.empty_like(Ud)
+    B = torch.empty_like(Ud)
+    C = torch.empty_like(Ud)
+    S.rk3_stage(sc, 1, Ud, Ud, A, dt)
+    S.rk3_stage(sc, 2, Ud, A, B, dt)
+    S.rk3_stage(sc, 3, Ud, B, C, dt)
+    U1 = O.rk3_stage(oc, 1, U, U, dt)
+    U2 = O.rk3_stage(oc, 2, U, U1, dt)
+    U3 = O.rk3_stage(oc, 3, U, U2, dt)
+    for g, o in ((A, U1), (B, U2), (C, U3)):
+        assert np.all(comp_rel(host(g), o) <= 1e-13)
+    ws = S.workspace(sc)
+    D = Ud.clone()
+    S.rk3_step(sc, D, dt, ws)
+    assert torch.equal(D, C)
+
+
+def test_hundred_steps_c1():
+    case = WL.taylor_green(32)
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    print("[parity] 100 steps TGV 32^3 oracle ...", flush=True)
+    Uo, t_o = O.advance(oc, U, 100, dt=1e-3)
+    sc = solver_cfg(case)
+    Ud = dev(U)
+    ws = S.workspace(sc)
+    t = S.advance(sc, Ud, 100, 1e-3, ws, t=0.0)
+    assert t == pytest.approx(t_o, rel=1e-15)
+    err = comp_rel(host(Ud), Uo)
+    print(f"[parity] 100 steps rel err {err}", flush=True)
+    assert np.all(err <= STEP_TOL), err
+
+
+def test_cfl_dt_and_advance_parity():
+    case = WL.taylor_green(24, viscous=True, reynolds=50.0)
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    sc = solver_cfg(case, cfl=0.5)
+    Ud = dev(U)
+    ws = S.workspace(sc)
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.compute_dt(sc, Ud, dtd, ws)
+    assert float(dtd.item()) == pytest.approx(O.compute_dt(oc, U, 0.5), rel=1e-14)
+    Uo, to = O.advance(oc, U, 5, dt=0.0, cfl=0.5)
+    t = S.advance(sc, Ud, 5, 0.0, ws, t=0.0)
+    assert t == pytest.approx(to, rel=1e-13)
+    assert np.all(comp_rel(host(Ud), Uo) <= 1e-12)
+
+
+def test_check_state_reports_bad_cells():
+    case = WL.taylor_green(16)
+    sc = solver_cfg(case)
+    U = dev(O.prim_to_cons(oracle_cfg(case), case.W))
+    ws = S.workspace(sc)
+    assert S.check_state(sc, U, ws).status == S.OK
+    V = U.clone()
+    V[0, 3, 2, 1] = -1.0
+    rep = S.check_state(sc, V, ws)
+    assert rep.status == S.EINADMISSIBLE and rep.first_bad_cell == (3 * 16 + 2) * 16 + 1 and rep.bad_count_clamped == 1
+    V[4, 0, 0, 5] = float("nan")
+    rep = S.check_state(sc, V, ws)
+    assert rep.status == S.ENONFINITE and rep.first_bad_cell == 5 and rep.bad_count_clamped == 2
+
+
+def test_fp32_error_against_fp64_oracle():
+    for name, case in [("euler_tgv32", WL.taylor_green(32)), ("ns_tgv32", WL.taylor_green(32, viscous=True)),
+                       ("dim_smooth", WL.smooth_random(12, 10, 9, model=WL.DIM, seed=23, gamma1=1.66))]:
+        oc = oracle_cfg(case)
+        U = O.prim_to_cons(oc, case.W)
+        Ro = O.rhs(oc, U, dt=1e-4)
+        sc = solver_cfg(case, dtype=S.F32)
+        Ud = dev(U, torch.float32)
+        Rd = S.rhs(sc, Ud, torch.empty_like(Ud), dt=1e-4)
+        err = comp_rel(host(Rd), Ro)
+        print(f"[fp32] rhs {name} rel err per component {err}", flush=True)
+        # single-precision rounding of the inputs alone costs ~1e-7 U / (dx R)
+        assert np.all(err < 5e-3), err
+
+
+@pytest.mark.parametrize("cfgname", ["ns_tgv_256", "dim_sbi_256x128x128"])
+def test_full_size_sampled_parity(cfgname):
+    if cfgname == "ns_tgv_256":
+        case = WL.taylor_green(256, viscous=True, with_field=False)
+        sc = solver_cfg(case)
+        U = S.init_state(sc, S.CASE_TGV, [0.1, 1.0, 1e-3], S.empty_state(sc), seed=2402)
+        dt = 1e-3
+    else:
+        case = WL.shock_bubble(256, 128, 128, with_field=False)
+        sc = solver_cfg(case)
+        rho2, u2, p2 = case.meta["post_shock"]
+        H = case.meta["H"]
+        params = [0.060, 0.090, H / 2, H / 2, 0.25 * H, WL.ALPHA_EPS, rho2, u2, p2, 1.2041, 101325.0, 0.1660]
+        U = S.init_state(sc, S.CASE_SBI, params, S.empty_state(sc))
+        dt = 2e-7
+    print(f"[parity] full size {cfgname}", flush=True)
+    R = S.rhs(sc, U, torch.empty_like(U), dt=dt)
+    U1 = torch.empty_like(U)
+    S.rk3_stage(sc, 1, U, U, U1, dt)
+    Uh = host(U)
+    Rh = host(R).reshape(sc.ncomp, -1)
+    U1h = host(U1).reshape(sc.ncomp, -1)
+    del R, U1, U
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(7)
+    n = sc.ncells
+    cells = np.concatenate([rng.integers(0, n, 300), [0, n - 1, sc.nx - 1, sc.nx * sc.ny - 1]])
+    if cfgname.startswith("dim"):
+        # a line of cells through the shock and the bubble centre
+        k = sc.nz // 2
+        j = sc.ny // 2
+        xs = np.arange(sc.nx)
+        cells = np.concatenate([cells, (k * sc.ny + j) * sc.nx + xs[::3]])
+    Ro = O.rhs_cells(oracle_cfg(case), Uh, cells, dt=dt)
+    scale = np.abs(Ro).max(axis=1)
+    for m in range(sc.ncomp):
+        err = np.abs(Rh[m, cells] - Ro[m]).max() / max(scale[m], 1e-300)
+        assert err <= RHS_TOL, (m, err)
+        ref1 = Uh.reshape(sc.ncomp, -1)[m, cells] + dt * Ro[m]
+        err1 = np.abs(U1h[m, cells] - ref1).max() / max(np.abs(ref1).max(), 1e-300)
+        assert err1 <= 1e-14, (m, err1)
