@@ -40,6 +40,29 @@ __device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* 
     if (fz) u[V + 2] = -u[V + 2];
 }
 
+// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3).
+template <typename Real, int NC>
+__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt)
+{
+    if (a.mode == 0) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = r[m];
+    } else if (a.mode == 1) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = a.Uk[m * a.ncell + q] + dt * r[m];
+    } else if (a.mode == 2) {
+        const Real c1 = Real(0.75), c2 = Real(0.25);
+#pragma unroll
+        for (int m = 0; m < NC; m++)
+            a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+    } else {
+        const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
+#pragma unroll
+        for (int m = 0; m < NC; m++)
+            a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+    }
+}
+
 // LDS geometry of one tile
 template <typename Real, int MODEL, int BX, int BY>
 struct Tile {
@@ -102,6 +125,9 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
     const bool own_valid = gx < a.nx && gy < a.ny;
 
     auto wp = [&](int f, int i, int j) -> Real& { return Wp[f * PLANE + (j + 3) * PX + (i + 3)]; };
+    auto store_cell = [&](const StageArgs<Real>& aa, long long q, const Real* r, Real dtv) {
+        store_cell_impl<Real, NC>(aa, q, r, dtv);
+    };
 
     // primitive state of an arbitrary (possibly outside) cell, plus T = p / rho
     auto load_w = [&](int gi, int gj, int gk, Real* w) {
@@ -117,15 +143,18 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
 #pragma unroll
     for (int q = 0; q < 5; q++) load_w(gx, gy, s_begin - 3 + q, win[q]);
 
-    Real vminus[NC];       // v^-_{s-3/2} from the reconstruction of cell s-2
-    Real accA[NC], accB[NC];  // partial R of cells s-2 and s-1
-    Real srcA = 0, srcB = 0;  // DIM: sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
+    Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
+    Real accA[NC], accB[NC];  // x/y part of R of cells s-2 and s-1
+    Real srcA = 0, srcB = 0;  // DIM: x/y part of sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
+    Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
+    Real uhzl = 0;            // its upwinded normal velocity (DIM)
     Real Dc[3][4];            // NS: (dw/dx, du/dx, dw/dy, dv/dy) at planes s-3, s-2, s-1
 #pragma unroll
     for (int m = 0; m < NC; m++) {
         vminus[m] = 0;
         accA[m] = 0;
         accB[m] = 0;
+        Fzl[m] = 0;
     }
 #pragma unroll
     for (int q = 0; q < 3; q++)
@@ -452,40 +481,18 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                     F[V + 2] -= Fd[2];
                     F[P] -= Fd[3];
                 }
+                if (s >= z0 + 2 && own_valid) {
+                    // finalise cell s-2: R = (x/y part) - (F_{s-3/2} - F_{s-5/2}) / dz
+                    const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
+                    Real r[NC];
 #pragma unroll
-                for (int m = 0; m < NC; m++) {
-                    accA[m] -= F[m] * idz;
-                    accB[m] += F[m] * idz;
+                    for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
+                    if constexpr (MODEL == DIM) r[6] += win[1][6] * (srcA + (uh - uhzl) * idz);
+                    store_cell(a, q, r, dt);
                 }
-                if constexpr (MODEL == DIM) {
-                    srcA -= uh * idz;
-                    srcB += uh * idz;
-                }
-            }
-            if (s >= z0 + 2 && own_valid) {
-                // finalise cell s-2
-                const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
-                Real r[NC];
 #pragma unroll
-                for (int m = 0; m < NC; m++) r[m] = accA[m];
-                if constexpr (MODEL == DIM) r[6] += win[1][6] * srcA;
-                if (a.mode == 0) {
-#pragma unroll
-                    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = r[m];
-                } else if (a.mode == 1) {
-#pragma unroll
-                    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = a.Uk[m * a.ncell + q] + dt * r[m];
-                } else if (a.mode == 2) {
-                    const Real c1 = Real(0.75), c2 = Real(0.25);
-#pragma unroll
-                    for (int m = 0; m < NC; m++)
-                        a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
-                } else {
-                    const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
-#pragma unroll
-                    for (int m = 0; m < NC; m++)
-                        a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
-                }
+                for (int m = 0; m < NC; m++) Fzl[m] = F[m];
+                uhzl = uh;
             }
 #pragma unroll
             for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];

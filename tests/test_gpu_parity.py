@@ -31,18 +31,39 @@ def host(t):
 
 
 def comp_rel(gpu, ref):
-    """Per-component max abs difference over max abs reference (reference-scale floor for zero components)."""
+    """Per-component max abs difference over max abs reference.  Momentum
+    components share the momentum vector's scale (a component that vanishes by
+    symmetry has only round-off as its own reference)."""
     nc = ref.shape[0]
     g = gpu.reshape(nc, -1)
     r = ref.reshape(nc, -1)
+    v0 = 2 if nc == 7 else 1
+    mom = np.abs(r[v0:v0 + 3]).max()
     scale_all = np.abs(r).max()
     out = []
     for m in range(nc):
         s = np.abs(r[m]).max()
+        if v0 <= m < v0 + 3:
+            s = mom
         if s < 1e-300:
             s = scale_all
         out.append(np.abs(g[m] - r[m]).max() / s)
     return np.array(out)
+
+
+def roundoff_floor(oc, U, dt, cells=None, trials=2, seed=1):
+    """Relative change of the oracle's own R when every input value moves by one
+    unit in the last place (random sign): the conditioning floor of the case.
+    In low-Mach flow the pressure flux (~1/(gamma Ma^2)) cancels in the flux
+    difference, so this floor can exceed 1e-12."""
+    rng = np.random.default_rng(seed)
+    R = O.rhs(oc, U, dt=dt) if cells is None else O.rhs_cells(oc, U, cells, dt=dt)
+    worst = np.zeros(U.shape[0])
+    for _ in range(trials):
+        Up = U * (1.0 + rng.choice([-1.0, 1.0], size=U.shape) * 2.0 ** -53)
+        Rp = O.rhs(oc, Up, dt=dt) if cells is None else O.rhs_cells(oc, Up, cells, dt=dt)
+        worst = np.maximum(worst, comp_rel(Rp, R))
+    return worst
 
 
 def oracle_cfg(case, **kw):
@@ -91,8 +112,11 @@ def test_rhs_parity(all_cases, name):
     Rd = torch.empty_like(Ud)
     S.rhs(sc, Ud, Rd, dt=dt)
     err = comp_rel(host(Rd), Ro)
-    print(f"[parity] rhs {name} rel err per component {err}", flush=True)
-    assert np.all(err <= RHS_TOL), err
+    floor = roundoff_floor(oc, U, dt)
+    tol = np.maximum(RHS_TOL, 2.0 * floor)
+    print(f"[parity] rhs {name} rel err {np.array2string(err, precision=2)} "
+          f"round-off floor {np.array2string(floor, precision=2)}", flush=True)
+    assert np.all(err <= tol), (err, floor)
 
 
 def test_prim_to_cons_parity(all_cases):
@@ -294,11 +318,22 @@ def test_full_size_sampled_parity(cfgname):
         j = sc.ny // 2
         xs = np.arange(sc.nx)
         cells = np.concatenate([cells, (k * sc.ny + j) * sc.nx + xs[::3]])
-    Ro = O.rhs_cells(oracle_cfg(case), Uh, cells, dt=dt)
-    scale = np.abs(Ro).max(axis=1)
+    oc = oracle_cfg(case)
+    Ro = O.rhs_cells(oc, Uh, cells, dt=dt)
+    Rg = Rh[:, cells]
+    err = comp_rel(Rg, Ro)
+    floor = roundoff_floor(oc, Uh, dt, cells=cells, trials=1)
+    tol = np.maximum(RHS_TOL, 2.0 * floor)
+    print(f"[parity] full size {cfgname}: rel err {np.array2string(err, precision=2)} "
+          f"round-off floor {np.array2string(floor, precision=2)}", flush=True)
     for m in range(sc.ncomp):
-        err = np.abs(Rh[m, cells] - Ro[m]).max() / max(scale[m], 1e-300)
-        assert err <= RHS_TOL, (m, err)
-        ref1 = Uh.reshape(sc.ncomp, -1)[m, cells] + dt * Ro[m]
-        err1 = np.abs(U1h[m, cells] - ref1).max() / max(np.abs(ref1).max(), 1e-300)
-        assert err1 <= 1e-14, (m, err1)
+        if err[m] > tol[m]:
+            d = np.abs(Rg[m] - Ro[m])
+            for w in np.argsort(d)[-5:]:
+                c = int(cells[w])
+                print(f"  comp {m} cell {c} (i={c % sc.nx}, j={(c // sc.nx) % sc.ny}, k={c // (sc.nx * sc.ny)}) "
+                      f"gpu={Rg[m, w]:.17e} oracle={Ro[m, w]:.17e}", flush=True)
+    assert np.all(err <= tol), (err, floor)
+    ref1 = Uh.reshape(sc.ncomp, -1)[:, cells] + dt * Ro
+    err1 = comp_rel(U1h[:, cells], ref1)
+    assert np.all(err1 <= 1e-14), err1
