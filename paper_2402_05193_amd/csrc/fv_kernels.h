@@ -14,6 +14,9 @@
 #ifndef TILE_BY
 #define TILE_BY 16
 #endif
+#ifndef WAVES_PER_EU
+#define WAVES_PER_EU 2
+#endif
 
 namespace fv {
 

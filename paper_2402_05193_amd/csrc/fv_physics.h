@@ -46,6 +46,40 @@ struct Tolerances {
     Real eps_rho, eps_rhoc2, eps_alpha;
 };
 
+// ---------------------------------------------------------------- arithmetic helpers
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (FP64: good to about an ulp for the positive normal arguments used here;
+// FP32: the single-precision estimates are used as they are).
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// sqrt(x) = x / sqrt(x), with one Newton correction of the product
+__device__ __forceinline__ double sqrt_fast(double x)
+{
+    const double y = rsqrt(x);
+    const double s = x * y;
+    return fma(0.5 * y, fma(-s, s, x), s);
+}
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---------------------------------------------------------------- EOS / maps
 template <typename Real, int MODEL>
 __device__ __forceinline__ Real density(const Real* w)
@@ -73,7 +107,7 @@ __device__ __forceinline__ Real rho_e(const Material<Real>& mat, const Real* w)
         mixture(mat, w[6], G, Pi);
         return G * w[P] + Pi;
     } else {
-        return (w[P] + mat.gpinf) / mat.gm1;
+        return (w[P] + mat.gpinf) * mat.iG1;
     }
 }
 
@@ -85,7 +119,7 @@ __device__ __forceinline__ Real rhoc2(const Material<Real>& mat, const Real* w)
     if constexpr (MODEL == DIM) {
         Real G, Pi;
         mixture(mat, w[6], G, Pi);
-        return ((G + Real(1)) * w[P] + Pi) / G;
+        return ((G + Real(1)) * w[P] + Pi) * rcp(G);
     } else {
         return mat.gamma * (w[P] + mat.pinf);
     }
@@ -106,18 +140,27 @@ __device__ __forceinline__ void cons_to_prim(const Material<Real>& mat, const Re
         w[0] = u[0];
         rho = u[0];
     }
-    w[V] = u[V] / rho;
-    w[V + 1] = u[V + 1] / rho;
-    w[V + 2] = u[V + 2] / rho;
+    const Real ir = rcp(rho);
+    w[V] = u[V] * ir;
+    w[V + 1] = u[V + 1] * ir;
+    w[V + 2] = u[V + 2] * ir;
     const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
     const Real re = u[P] - ke;
     if constexpr (MODEL == DIM) {
         Real G, Pi;
         mixture(mat, u[6], G, Pi);
-        w[P] = (re - Pi) / G;
+        w[P] = (re - Pi) * rcp(G);
     } else {
         w[P] = mat.gm1 * re - mat.gpinf;
     }
+}
+
+// L_{U->W} that also returns 1/rho
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real cons_to_prim_ir(const Material<Real>& mat, const Real* u, Real* w)
+{
+    cons_to_prim<Real, MODEL>(mat, u, w);
+    return rcp(density<Real, MODEL>(w));
 }
 
 // L_{W->U}
@@ -164,21 +207,46 @@ __device__ __forceinline__ void weno5z_pair(Real a, Real b, Real c, Real d, Real
     const Real b1 = k13 * t1 * t1 + q * s1 * s1;
     const Real b2 = k13 * t2 * t2 + q * s2 * s2;
     const Real tau = fabs(b0 - b2);
-    const Real g0 = Real(1) + tau / (b0 + eps);
-    const Real g1 = Real(1) + tau / (b1 + eps);
-    const Real g2 = Real(1) + tau / (b2 + eps);
+    const Real e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    Real r0, r1, r2;
+    if constexpr (sizeof(Real) == 8) {
+        // one reciprocal for the three indicators: 1/e_k from 1/(e0 e1 e2)
+        const Real p01 = e0 * e1;
+        const Real R = rcp(p01 * e2);
+        const Real t = e2 * R;
+        r2 = p01 * R;
+        r0 = e1 * t;
+        r1 = e0 * t;
+    } else {
+        r0 = rcp(e0);
+        r1 = rcp(e1);
+        r2 = rcp(e2);
+    }
+    const Real g0 = fma(tau, r0, Real(1));
+    const Real g1 = fma(tau, r1, Real(1));
+    const Real g2 = fma(tau, r2, Real(1));
     // candidate values (times 6)
     const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
     const Real p1 = -b + Real(5) * c + Real(2) * d;
     const Real p2 = Real(2) * c + Real(5) * d - e;
-    const Real r0 = Real(2) * e - Real(7) * d + Real(11) * c;
-    const Real r1 = -d + Real(5) * c + Real(2) * b;
-    const Real r2 = Real(2) * c + Real(5) * b - a;
+    const Real u0 = Real(2) * e - Real(7) * d + Real(11) * c;
+    const Real u1 = -d + Real(5) * c + Real(2) * b;
+    const Real u2 = Real(2) * c + Real(5) * b - a;
     // alpha scaled by 10: (1, 6, 3) g for vm and (3, 6, 1) g reversed for vp
-    const Real m0 = g0, m1 = Real(6) * g1, m2 = Real(3) * g2;
-    const Real n0 = g2, n2 = Real(3) * g0;
-    vm = (m0 * p0 + m1 * p1 + m2 * p2) / (Real(6) * (m0 + m1 + m2));
-    vp = (n0 * r0 + m1 * r1 + n2 * r2) / (Real(6) * (n0 + m1 + n2));
+    const Real m1 = Real(6) * g1, m2 = Real(3) * g2, n2 = Real(3) * g0;
+    const Real dm = Real(6) * (g0 + m1 + m2);
+    const Real dp = Real(6) * (g2 + m1 + n2);
+    Real idm, idp;
+    if constexpr (sizeof(Real) == 8) {
+        const Real R = rcp(dm * dp);
+        idm = dp * R;
+        idp = dm * R;
+    } else {
+        idm = rcp(dm);
+        idp = rcp(dp);
+    }
+    vm = (g0 * p0 + m1 * p1 + m2 * p2) * idm;
+    vp = (g2 * u0 + m1 * u1 + n2 * u2) * idp;
 }
 
 // ---------------------------------------------------------------- HLLC
@@ -190,11 +258,11 @@ template <typename Real, int MODEL, int DIR>
 __device__ __forceinline__ void hllc_side(const Material<Real>& mat, const Real* w, Real rho, Real un, Real sK,
                                           Real sw, Real sstar, Real* F, Real& uh)
 {
-    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P, NC = Layout<MODEL>::NC;
+    constexpr int V = Layout<MODEL>::V, P = Layout<MODEL>::P;
     const Real p = w[P];
-    const Real r = Real(1) / (sK - sstar);
-    const Real fac = (sK - un) * r;          // (s^K - u^K)/(s^K - s*)
-    const Real q = un + sw * (fac - Real(1)); // flux of any advected density per unit density
+    const Real r = rcp(sK - sstar);
+    const Real fac = (sK - un) * r;           // (s^K - u^K)/(s^K - s*)
+    const Real q = un + sw * (fac - Real(1));  // flux of any advected density per unit density
     const Real ke = Real(0.5) * rho * (w[V] * w[V] + w[V + 1] * w[V + 1] + w[V + 2] * w[V + 2]);
     const Real E = rho_e<Real, MODEL>(mat, w) + ke;
     if constexpr (MODEL == DIM) {
@@ -217,7 +285,6 @@ __device__ __forceinline__ void hllc_side(const Material<Real>& mat, const Real*
     const Real Estar = fac * (E + ds * rho * sstar) + ds * p * r;
     F[P] = un * (E + p) + sw * (Estar - E);
     uh = q;
-    (void)NC;
 }
 
 template <typename Real, int MODEL, int DIR>
@@ -227,26 +294,31 @@ __device__ __forceinline__ void hllc(const Material<Real>& mat, const Real* wl, 
     const Real rhoL = density<Real, MODEL>(wl), rhoR = density<Real, MODEL>(wr);
     const Real uL = wl[V + DIR], uR = wr[V + DIR];
     const Real pL = wl[P], pR = wr[P];
-    const Real c2L = rhoc2<Real, MODEL>(mat, wl) / rhoL;
-    const Real c2R = rhoc2<Real, MODEL>(mat, wr) / rhoR;
-    const Real cL = sqrt(c2L), cR = sqrt(c2R);
-    const Real sqL = sqrt(rhoL), sqR = sqrt(rhoR);
-    const Real isum = Real(1) / (sqL + sqR);
+    // sqrt(rho) and 1/rho from one reciprocal square root per side
+    const Real yL = rsqrt(rhoL), yR = rsqrt(rhoR);
+    const Real sqL = rhoL * yL, sqR = rhoR * yR;
+    const Real rc2L = rhoc2<Real, MODEL>(mat, wl), rc2R = rhoc2<Real, MODEL>(mat, wr);
+    const Real c2L = rc2L * (yL * yL), c2R = rc2R * (yR * yR);
+    const Real cL = sqrt_fast(rc2L) * yL, cR = sqrt_fast(rc2R) * yR;
+    const Real isum = rcp(sqL + sqR);
     const Real ubar = (sqL * uL + sqR * uR) * isum;
     const Real du = uR - uL;
     const Real cbar2 = (sqL * c2L + sqR * c2R) * isum + Real(0.5) * sqL * sqR * isum * isum * du * du;
-    const Real cbar = sqrt(cbar2);
+    const Real cbar = sqrt_fast(cbar2);
     const Real sL = fmin(ubar - cbar, uL - cL);
     const Real sR = fmax(ubar + cbar, uR + cR);
     const Real mL = rhoL * (sL - uL), mR = rhoR * (sR - uR);
-    const Real sstar = ((pR - pL) + (mL * uL - mR * uR)) / (mL - mR);
+    const Real sstar = ((pR - pL) + (mL * uL - mR * uR)) * rcp(mL - mR);
     const Real sminus = fmin(Real(0), sL), splus = fmax(Real(0), sR);
-    // one side unless s* == 0 (sgn(0) = 0 averages both)
+    // upwind side by operand selection (sgn(0) = 0 averages both sides below)
     const bool left = !(sstar < Real(0));
+    Real ws[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) ws[m] = left ? wl[m] : wr[m];
     Real Fa[NC];
     Real uha;
-    if (left) hllc_side<Real, MODEL, DIR>(mat, wl, rhoL, uL, sL, sminus, sstar, Fa, uha);
-    else hllc_side<Real, MODEL, DIR>(mat, wr, rhoR, uR, sR, splus, sstar, Fa, uha);
+    hllc_side<Real, MODEL, DIR>(mat, ws, left ? rhoL : rhoR, left ? uL : uR, left ? sL : sR,
+                                left ? sminus : splus, sstar, Fa, uha);
     if (sstar == Real(0)) {
         Real Fb[NC];
         Real uhb;
@@ -370,6 +442,60 @@ __device__ __forceinline__ void viscous_flux(const Real (*q)[4], const Real* dt1
     const Real g_t2n = ifc(dt2n[0], dt2n[1], dt2n[2], dt2n[3]);
     const Real g_t1t1 = ifc(dt1t1[0], dt1t1[1], dt1t1[2], dt1t1[3]);
     const Real g_t2t2 = ifc(dt2t2[0], dt2t2[1], dt2t2[2], dt2t2[3]);
+    const Real div = dn[DIR] + g_t1t1 + g_t2t2;
+    Real tau[3];
+    tau[DIR] = mu * (Real(2) * dn[DIR]) - Real(2.0 / 3.0) * mu * div;
+    tau[T1] = mu * (g_t1n + dn[T1]);
+    tau[T2] = mu * (g_t2n + dn[T2]);
+    Fd[0] = tau[0];
+    Fd[1] = tau[1];
+    Fd[2] = tau[2];
+    Fd[3] = vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2] + kappa * dn[3];
+}
+
+// The flux from face gradients already formed: dn[c] = d q_c / d x_n (c = u, v,
+// w, T), vf = face velocity, and the interpolated tangential derivatives
+// g_t1n = d u_n/d x_t1, g_t2n = d u_n/d x_t2, g_t1t1, g_t2t2.
+template <typename Real, int DIR>
+__device__ __forceinline__ void viscous_flux_from_gradients(const Real* dn, const Real* vf, Real g_t1n, Real g_t2n,
+                                                            Real g_t1t1, Real g_t2t2, Real mu, Real kappa, Real* Fd)
+{
+    constexpr int T1 = DIR == 0 ? 1 : 0;
+    constexpr int T2 = DIR == 2 ? 1 : 2;
+    const Real div = dn[DIR] + g_t1t1 + g_t2t2;
+    Real tau[3];
+    tau[DIR] = mu * (Real(2) * dn[DIR]) - Real(2.0 / 3.0) * mu * div;
+    tau[T1] = mu * (g_t1n + dn[T1]);
+    tau[T2] = mu * (g_t2n + dn[T2]);
+    Fd[0] = tau[0];
+    Fd[1] = tau[1];
+    Fd[2] = tau[2];
+    Fd[3] = vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2] + kappa * dn[3];
+}
+
+// The same flux reading its inputs from LDS one quantity at a time.
+//  vel: &u at the first of the four cells (u, v, w are `fstride` apart),
+//  temp: &T at the first cell; consecutive cells are `cstride` apart.
+//  t1n, t2n, t1t1, t2t2: d u_n/d x_t1, d u_n/d x_t2, d u_t1/d x_t1, d u_t2/d x_t2
+//  at the first cell, consecutive cells `dstride` apart.
+template <typename Real, int DIR>
+__device__ __forceinline__ void viscous_flux_lds(const Real* vel, const Real* temp, int cstride, int fstride,
+                                                 const Real* t1n, const Real* t2n, const Real* t1t1,
+                                                 const Real* t2t2, int dstride, Real mu, Real kappa, Real inv24h,
+                                                 Real* Fd)
+{
+    constexpr int T1 = DIR == 0 ? 1 : 0;
+    constexpr int T2 = DIR == 2 ? 1 : 2;
+    Real dn[4], vf[3];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const Real* q = c < 3 ? vel + c * fstride : temp;
+        const Real a = q[0], b = q[cstride], cc = q[2 * cstride], d = q[3 * cstride];
+        dn[c] = dface(a, b, cc, d, inv24h);
+        if (c < 3) vf[c] = ifc(a, b, cc, d);
+    }
+    auto itp = [&](const Real* t) { return ifc(t[0], t[dstride], t[2 * dstride], t[3 * dstride]); };
+    const Real g_t1n = itp(t1n), g_t2n = itp(t2n), g_t1t1 = itp(t1t1), g_t2t2 = itp(t2t2);
     const Real div = dn[DIR] + g_t1t1 + g_t2t2;
     Real tau[3];
     tau[DIR] = mu * (Real(2) * dn[DIR]) - Real(2.0 / 3.0) * mu * div;

@@ -68,7 +68,8 @@ template <typename Real, int MODEL, int BX, int BY>
 struct Tile {
     static constexpr int NC = Layout<MODEL>::NC;
     static constexpr bool VISC = MODEL == NS;
-    static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho)
+    static constexpr int NT = BX * BY;
+    static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho) of the LDS plane
     static constexpr int PX = BX + 6, PY = BY + 6;  // plane with 3-cell halo
     static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
     static constexpr int NFMAX = NFX > NFY ? NFX : NFY;
@@ -79,19 +80,24 @@ struct Tile {
     static constexpr int DZ_SIZE = VISC ? 2 * RX + 2 * RY : 0;    // d/dz of (u,w) on RX, (v,w) on RY
     static constexpr int DT_SIZE = VISC ? 2 * (RX > RY ? RX : RY) : 0;  // in-plane tangential d/dx_t
     static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : 0);
+    // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
+    // five-equation model keeps them in registers instead (LDS budget)
+    static constexpr bool ACC_LDS = MODEL != DIM;
+    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NT : 0;
     static constexpr size_t bytes()
     {
-        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE);
+        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE);
     }
 };
 
-template <typename Real, int MODEL, int BX, int BY>
-__global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
+template <typename Real, int MODEL, bool POS, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
 {
     using L = Layout<MODEL>;
     using TL = Tile<Real, MODEL, BX, BY>;
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
+    constexpr bool ACC_LDS = TL::ACC_LDS;
     constexpr int NW = TL::NW, PX = TL::PX, PY = TL::PY;
     constexpr int NT = BX * BY;
     constexpr int PLANE = PY * PX;
@@ -103,11 +109,11 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
     Real* DZX = UHB + TL::UH_SIZE;  // [2][BY][BX+4]   (u, w) d/dz, x-face region
     Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
     Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
+    Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NT]     x/y partial sums of R
 
     const Material<Real> mat = a.mat;
     const Tolerances<Real> tol = a.tol;
     const Real weps = a.weno_eps;
-    const bool pos = a.positivity != 0;
     const Real dt = a.dt_dev ? Real(*a.dt_dev) : Real(a.dt);
 
     const int tid = threadIdx.x;
@@ -125,26 +131,27 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
     const bool own_valid = gx < a.nx && gy < a.ny;
 
     auto wp = [&](int f, int i, int j) -> Real& { return Wp[f * PLANE + (j + 3) * PX + (i + 3)]; };
-    auto store_cell = [&](const StageArgs<Real>& aa, long long q, const Real* r, Real dtv) {
-        store_cell_impl<Real, NC>(aa, q, r, dtv);
-    };
 
-    // primitive state of an arbitrary (possibly outside) cell, plus T = p / rho
+    // primitive state of an arbitrary (possibly outside) cell
     auto load_w = [&](int gi, int gj, int gk, Real* w) {
         Real u[NC];
         load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V);
         cons_to_prim<Real, MODEL>(mat, u, w);
-        if constexpr (VISC) w[NC] = w[P] / w[0];
+    };
+    auto stage_w = [&](int i, int j, const Real* w) {
+#pragma unroll
+        for (int f = 0; f < NC; f++) wp(f, i, j) = w[f];
+        if constexpr (VISC) wp(NC, i, j) = w[P] * rcp(w[0]);  // T = p / rho
     };
 
     // register window W(s-3 .. s+2) of the own column
-    Real win[6][NW];
+    Real win[6][NC];
     const int s_begin = VISC ? z0 - 2 : z0;
 #pragma unroll
     for (int q = 0; q < 5; q++) load_w(gx, gy, s_begin - 3 + q, win[q]);
 
     Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
-    Real accA[NC], accB[NC];  // x/y part of R of cells s-2 and s-1
+    Real accA[NC], accB[NC];  // x/y part of R of cells s-2, s-1 (register variant)
     Real srcA = 0, srcB = 0;  // DIM: x/y part of sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
     Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
     Real uhzl = 0;            // its upwinded normal velocity (DIM)
@@ -179,8 +186,7 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
         if (need_plane) {
             __syncthreads();
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
-#pragma unroll
-            for (int f = 0; f < NW; f++) wp(f, tx, ty) = win[3][f];
+            stage_w(tx, ty, win[3]);
             for (int h = tid; h < TL::NHALO; h += NT) {
                 int i, j;
                 if (h < 6 * BY) {
@@ -198,10 +204,9 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                     i = ci < 2 ? ci - 2 : BX + ci - 2;
                     j = cj < 2 ? cj - 2 : BY + cj - 2;
                 }
-                Real w[NW];
+                Real w[NC];
                 load_w(x0 + i, y0 + j, s, w);
-#pragma unroll
-                for (int f = 0; f < NW; f++) wp(f, i, j) = w[f];
+                stage_w(i, j, w);
             }
             if constexpr (VISC) {
                 if (xy) {
@@ -228,14 +233,24 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                             const int k = hh / BX;
                             j = k < 2 ? k - 2 : BY + k - 2;
                         }
-                        Real w[4][NW];
-                        load_w(x0 + i, y0 + j, s - 2, w[0]);
-                        load_w(x0 + i, y0 + j, s - 1, w[1]);
-                        load_w(x0 + i, y0 + j, s + 1, w[2]);
-                        load_w(x0 + i, y0 + j, s + 2, w[3]);
+                        // velocities of planes s-2, s-1, s+1, s+2 (density and momenta only)
+                        Real vel[4][3];
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const int dk = k < 2 ? k - 2 : k - 1;
+                            bool fx = false, fy = false, fz = false;
+                            const int ii = map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
+                            const int jj = map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
+                            const int kk = map_index(s + dk, a.nz, a.bc[4], a.bc[5], fz);
+                            const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
+                            const Real ir = rcp(a.Uk[qq]);
+                            vel[k][0] = (fx ? -a.Uk[V * a.ncell + qq] : a.Uk[V * a.ncell + qq]) * ir;
+                            vel[k][1] = (fy ? -a.Uk[(V + 1) * a.ncell + qq] : a.Uk[(V + 1) * a.ncell + qq]) * ir;
+                            vel[k][2] = (fz ? -a.Uk[(V + 2) * a.ncell + qq] : a.Uk[(V + 2) * a.ncell + qq]) * ir;
+                        }
                         Real d[3];
 #pragma unroll
-                        for (int c = 0; c < 3; c++) d[c] = dcell(w[0][V + c], w[1][V + c], w[2][V + c], w[3][V + c], i12);
+                        for (int c = 0; c < 3; c++) d[c] = dcell(vel[0][c], vel[1][c], vel[2][c], vel[3][c], i12);
                         if (h < 4 * BY) {
                             DZX[0 * TL::RX + j * (BX + 4) + i + 2] = d[0];
                             DZX[1 * TL::RX + j * (BX + 4) + i + 2] = d[2];
@@ -247,181 +262,6 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                 }
             }
             __syncthreads();
-
-            if (xy) {
-                // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
-                Real* FL = FB;
-                Real* FR = FB + NC * TL::NFX;
-                for (int t = tid; t < (BX + 2) * BY; t += NT) {
-                    const int j = t / (BX + 2), i = t % (BX + 2) - 1;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        Real vm, vp;
-                        weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
-                                    weps, vm, vp);
-                        if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
-                        if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
-                    }
-                }
-                if constexpr (VISC) {
-                    const Real i12 = a.inv12dy;
-                    for (int t = tid; t < TL::RX; t += NT) {
-                        const int j = t / (BX + 4), i = t % (BX + 4) - 2;
-                        DT[t] = dcell(wp(V, i, j - 2), wp(V, i, j - 1), wp(V, i, j + 1), wp(V, i, j + 2), i12);
-                        DT[TL::RX + t] =
-                            dcell(wp(V + 1, i, j - 2), wp(V + 1, i, j - 1), wp(V + 1, i, j + 1), wp(V + 1, i, j + 2), i12);
-                    }
-                }
-                __syncthreads();
-                // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
-                for (int t = tid; t < TL::NFX; t += NT) {
-                    const int j = t / (BX + 1), f = t % (BX + 1);
-                    Real wl[NC], wr[NC], F[NC], uh;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        wl[m] = FL[m * TL::NFX + t];
-                        wr[m] = FR[m * TL::NFX + t];
-                    }
-                    if (pos) {
-                        Real wi[NC], wj[NC];
-#pragma unroll
-                        for (int m = 0; m < NC; m++) {
-                            wi[m] = wp(m, f - 1, j);
-                            wj[m] = wp(m, f, j);
-                        }
-                        if (inadmissible_w<Real, MODEL>(mat, tol, wl))
-#pragma unroll
-                            for (int m = 0; m < NC; m++) wl[m] = wi[m];
-                        if (inadmissible_w<Real, MODEL>(mat, tol, wr))
-#pragma unroll
-                            for (int m = 0; m < NC; m++) wr[m] = wj[m];
-                        hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
-                        if (flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx))
-                            hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
-                    } else {
-                        hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
-                    }
-                    if constexpr (VISC) {
-                        Real q[4][4], d1[4], d2[4], d3[4], d4[4];
-#pragma unroll
-                        for (int c = 0; c < 4; c++) {
-                            const int i = f - 2 + c;
-                            q[c][0] = wp(V, i, j);
-                            q[c][1] = wp(V + 1, i, j);
-                            q[c][2] = wp(V + 2, i, j);
-                            q[c][3] = wp(NC, i, j);
-                            const int r = j * (BX + 4) + i + 2;
-                            d1[c] = DT[r];                 // du/dy
-                            d2[c] = DZX[r];                // du/dz
-                            d3[c] = DT[TL::RX + r];        // dv/dy
-                            d4[c] = DZX[TL::RX + r];       // dw/dz
-                        }
-                        Real Fd[4];
-                        viscous_flux<Real, 0>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dx, Fd);
-                        F[V] -= Fd[0];
-                        F[V + 1] -= Fd[1];
-                        F[V + 2] -= Fd[2];
-                        F[P] -= Fd[3];
-                    }
-#pragma unroll
-                    for (int m = 0; m < NC; m++) FL[m * TL::NFX + t] = F[m];
-                    if constexpr (MODEL == DIM) UHB[t] = uh;
-                }
-                __syncthreads();
-                // ---- P3: x divergence of the own cell
-                {
-                    const int fl = ty * (BX + 1) + tx;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) accC[m] = -(FL[m * TL::NFX + fl + 1] - FL[m * TL::NFX + fl]) * idx;
-                    if constexpr (MODEL == DIM) srcC = (UHB[fl + 1] - UHB[fl]) * idx;
-                }
-                __syncthreads();
-                // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
-                Real* GL = FB;
-                Real* GR = FB + NC * TL::NFY;
-                for (int t = tid; t < BX * (BY + 2); t += NT) {
-                    const int i = t % BX, j = t / BX - 1;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        Real vm, vp;
-                        weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
-                                    weps, vm, vp);
-                        if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
-                        if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
-                    }
-                }
-                if constexpr (VISC) {
-                    const Real i12 = a.inv12dx;
-                    for (int t = tid; t < TL::RY; t += NT) {
-                        const int i = t % BX, j = t / BX - 2;
-                        DT[t] = dcell(wp(V + 1, i - 2, j), wp(V + 1, i - 1, j), wp(V + 1, i + 1, j), wp(V + 1, i + 2, j), i12);
-                        DT[TL::RY + t] = dcell(wp(V, i - 2, j), wp(V, i - 1, j), wp(V, i + 1, j), wp(V, i + 2, j), i12);
-                    }
-                }
-                __syncthreads();
-                // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
-                for (int t = tid; t < TL::NFY; t += NT) {
-                    const int i = t % BX, f = t / BX;
-                    Real wl[NC], wr[NC], F[NC], uh;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        wl[m] = GL[m * TL::NFY + t];
-                        wr[m] = GR[m * TL::NFY + t];
-                    }
-                    if (pos) {
-                        Real wi[NC], wj[NC];
-#pragma unroll
-                        for (int m = 0; m < NC; m++) {
-                            wi[m] = wp(m, i, f - 1);
-                            wj[m] = wp(m, i, f);
-                        }
-                        if (inadmissible_w<Real, MODEL>(mat, tol, wl))
-#pragma unroll
-                            for (int m = 0; m < NC; m++) wl[m] = wi[m];
-                        if (inadmissible_w<Real, MODEL>(mat, tol, wr))
-#pragma unroll
-                            for (int m = 0; m < NC; m++) wr[m] = wj[m];
-                        hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
-                        if (flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy))
-                            hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
-                    } else {
-                        hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
-                    }
-                    if constexpr (VISC) {
-                        Real q[4][4], d1[4], d2[4], d3[4], d4[4];
-#pragma unroll
-                        for (int c = 0; c < 4; c++) {
-                            const int j = f - 2 + c;
-                            q[c][0] = wp(V, i, j);
-                            q[c][1] = wp(V + 1, i, j);
-                            q[c][2] = wp(V + 2, i, j);
-                            q[c][3] = wp(NC, i, j);
-                            const int r = (j + 2) * BX + i;
-                            d1[c] = DT[r];                 // dv/dx
-                            d2[c] = DZY[r];                // dv/dz
-                            d3[c] = DT[TL::RY + r];        // du/dx
-                            d4[c] = DZY[TL::RY + r];       // dw/dz
-                        }
-                        Real Fd[4];
-                        viscous_flux<Real, 1>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dy, Fd);
-                        F[V] -= Fd[0];
-                        F[V + 1] -= Fd[1];
-                        F[V + 2] -= Fd[2];
-                        F[P] -= Fd[3];
-                    }
-#pragma unroll
-                    for (int m = 0; m < NC; m++) GL[m * TL::NFY + t] = F[m];
-                    if constexpr (MODEL == DIM) UHB[t] = uh;
-                }
-                __syncthreads();
-                // ---- P6: y divergence of the own cell
-                {
-                    const int fl = ty * BX + tx;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) accC[m] -= (GL[m * TL::NFY + fl + BX] - GL[m * TL::NFY + fl]) * idy;
-                    if constexpr (MODEL == DIM) srcC += (UHB[fl + BX] - UHB[fl]) * idy;
-                }
-            }
             if constexpr (VISC) {
                 // in-plane derivatives of the own column for the z faces
                 const Real i12x = a.inv12dx, i12y = a.inv12dy;
@@ -432,7 +272,7 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
             }
         }
 
-        // ---- z work of the own column (registers only)
+        // ---- z work of the own column (registers only): finalises cell s-2
         if (s >= z0) {
             // reconstruction of cell s-1 from W(s-3 .. s+1) = win[0..4]
             Real vm_new[NC], vp[NC];
@@ -441,13 +281,33 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                 weno5z_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], weps, vm_new[m], vp[m]);
             if (s >= z0 + 1) {
                 // z face s-3/2 between cells s-2 (win[1]) and s-1 (win[2])
+                Real Fd[4];
+                if constexpr (VISC) {
+                    // viscous part first: its inputs are the window and the carried derivatives
+                    const Real i24 = a.inv24dz;
+                    Real dn[4], vf[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const Real q0 = win[0][V + c], q1 = win[1][V + c], q2 = win[2][V + c], q3 = win[3][V + c];
+                        dn[c] = dface(q0, q1, q2, q3, i24);
+                        vf[c] = ifc(q0, q1, q2, q3);
+                    }
+                    dn[3] = dface(win[0][P] * rcp(win[0][0]), win[1][P] * rcp(win[1][0]), win[2][P] * rcp(win[2][0]),
+                                  win[3][P] * rcp(win[3][0]), i24);
+                    const Real g_xw = ifc(Dc[0][0], Dc[1][0], Dc[2][0], Dnew[0]);  // dw/dx
+                    const Real g_yw = ifc(Dc[0][2], Dc[1][2], Dc[2][2], Dnew[2]);  // dw/dy
+                    const Real g_xu = ifc(Dc[0][1], Dc[1][1], Dc[2][1], Dnew[1]);  // du/dx
+                    const Real g_yv = ifc(Dc[0][3], Dc[1][3], Dc[2][3], Dnew[3]);  // dv/dy
+                    viscous_flux_from_gradients<Real, 2>(dn, vf, g_xw, g_yw, g_xu, g_yv, a.mu, a.kappa, Fd);
+                    __builtin_amdgcn_sched_barrier(0);  // keep the two flux parts from interleaving (registers)
+                }
                 Real wl[NC], wr[NC], F[NC], uh;
 #pragma unroll
                 for (int m = 0; m < NC; m++) {
                     wl[m] = vminus[m];
                     wr[m] = vp[m];
                 }
-                if (pos) {
+                if constexpr (POS) {
                     if (inadmissible_w<Real, MODEL>(mat, tol, wl))
 #pragma unroll
                         for (int m = 0; m < NC; m++) wl[m] = win[1][m];
@@ -461,21 +321,6 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                     hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
                 }
                 if constexpr (VISC) {
-                    Real q[4][4], d1[4], d2[4], d3[4], d4[4];
-#pragma unroll
-                    for (int c = 0; c < 4; c++) {
-                        q[c][0] = win[c][V];
-                        q[c][1] = win[c][V + 1];
-                        q[c][2] = win[c][V + 2];
-                        q[c][3] = win[c][NC];
-                        const Real* D = c < 3 ? Dc[c] : Dnew;
-                        d1[c] = D[0];  // dw/dx
-                        d2[c] = D[2];  // dw/dy
-                        d3[c] = D[1];  // du/dx
-                        d4[c] = D[3];  // dv/dy
-                    }
-                    Real Fd[4];
-                    viscous_flux<Real, 2>(q, d1, d2, d3, d4, a.mu, a.kappa, a.inv24dz, Fd);
                     F[V] -= Fd[0];
                     F[V + 1] -= Fd[1];
                     F[V + 2] -= Fd[2];
@@ -485,10 +330,16 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
                     // finalise cell s-2: R = (x/y part) - (F_{s-3/2} - F_{s-5/2}) / dz
                     const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
                     Real r[NC];
+                    if constexpr (ACC_LDS) {
+                        const Real* slot = ACC + (s & 1) * NC * NT + tid;
 #pragma unroll
-                    for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
+                        for (int m = 0; m < NC; m++) r[m] = slot[m * NT] - (F[m] - Fzl[m]) * idz;
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
+                    }
                     if constexpr (MODEL == DIM) r[6] += win[1][6] * (srcA + (uh - uhzl) * idz);
-                    store_cell(a, q, r, dt);
+                    store_cell_impl<Real, NC>(a, q, r, dt);
                 }
 #pragma unroll
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
@@ -497,11 +348,173 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
 #pragma unroll
             for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];
         }
-        // rotate carries
+
+        if (xy) {
+            Real* slot = ACC + (s & 1) * NC * NT + tid;  // partial sums of cell s (ACC_LDS)
+            // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
+            Real* FL = FB;
+            Real* FR = FB + NC * TL::NFX;
+            for (int t = tid; t < (BX + 2) * BY; t += NT) {
+                const int j = t / (BX + 2), i = t % (BX + 2) - 1;
 #pragma unroll
-        for (int m = 0; m < NC; m++) {
-            accA[m] = accB[m];
-            accB[m] = accC[m];
+                for (int m = 0; m < NC; m++) {
+                    Real vm, vp;
+                    weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
+                                weps, vm, vp);
+                    if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
+                    if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                }
+            }
+            if constexpr (VISC) {
+                const Real i12 = a.inv12dy;
+                for (int t = tid; t < TL::RX; t += NT) {
+                    const int j = t / (BX + 4), i = t % (BX + 4) - 2;
+                    DT[t] = dcell(wp(V, i, j - 2), wp(V, i, j - 1), wp(V, i, j + 1), wp(V, i, j + 2), i12);
+                    DT[TL::RX + t] =
+                        dcell(wp(V + 1, i, j - 2), wp(V + 1, i, j - 1), wp(V + 1, i, j + 1), wp(V + 1, i, j + 2), i12);
+                }
+            }
+            __syncthreads();
+            // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
+            for (int t = tid; t < TL::NFX; t += NT) {
+                const int j = t / (BX + 1), f = t % (BX + 1);
+                Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    wl[m] = FL[m * TL::NFX + t];
+                    wr[m] = FR[m * TL::NFX + t];
+                }
+                if constexpr (POS) {
+                    Real wi[NC], wj[NC];
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wi[m] = wp(m, f - 1, j);
+                        wj[m] = wp(m, f, j);
+                    }
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                    hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx))
+                        hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
+                } else {
+                    hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    const int r0 = j * (BX + 4) + f;  // region index of cell f-2
+                    Real Fd[4];
+                    viscous_flux_lds<Real, 0>(&wp(V, f - 2, j), &wp(NC, f - 2, j), 1, PLANE, DT + r0, DZX + r0,
+                                              DT + TL::RX + r0, DZX + TL::RX + r0, 1, a.mu, a.kappa, a.inv24dx, Fd);
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) FL[m * TL::NFX + t] = F[m];
+                if constexpr (MODEL == DIM) UHB[t] = uh;
+            }
+            __syncthreads();
+            // ---- P3: x divergence of the own cell
+            {
+                const int fl = ty * (BX + 1) + tx;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    const Real v = -(FL[m * TL::NFX + fl + 1] - FL[m * TL::NFX + fl]) * idx;
+                    if constexpr (ACC_LDS) slot[m * NT] = v;
+                    else accC[m] = v;
+                }
+                if constexpr (MODEL == DIM) srcC = (UHB[fl + 1] - UHB[fl]) * idx;
+            }
+            __syncthreads();
+            // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
+            Real* GL = FB;
+            Real* GR = FB + NC * TL::NFY;
+            for (int t = tid; t < BX * (BY + 2); t += NT) {
+                const int i = t % BX, j = t / BX - 1;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    Real vm, vp;
+                    weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
+                                weps, vm, vp);
+                    if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
+                    if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                }
+            }
+            if constexpr (VISC) {
+                const Real i12 = a.inv12dx;
+                for (int t = tid; t < TL::RY; t += NT) {
+                    const int i = t % BX, j = t / BX - 2;
+                    DT[t] = dcell(wp(V + 1, i - 2, j), wp(V + 1, i - 1, j), wp(V + 1, i + 1, j), wp(V + 1, i + 2, j), i12);
+                    DT[TL::RY + t] = dcell(wp(V, i - 2, j), wp(V, i - 1, j), wp(V, i + 1, j), wp(V, i + 2, j), i12);
+                }
+            }
+            __syncthreads();
+            // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
+            for (int t = tid; t < TL::NFY; t += NT) {
+                const int i = t % BX, f = t / BX;
+                Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    wl[m] = GL[m * TL::NFY + t];
+                    wr[m] = GR[m * TL::NFY + t];
+                }
+                if constexpr (POS) {
+                    Real wi[NC], wj[NC];
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wi[m] = wp(m, i, f - 1);
+                        wj[m] = wp(m, i, f);
+                    }
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                    hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy))
+                        hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
+                } else {
+                    hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    const int r0 = f * BX + i;  // region index of cell f-2
+                    Real Fd[4];
+                    viscous_flux_lds<Real, 1>(&wp(V, i, f - 2), &wp(NC, i, f - 2), PX, PLANE, DT + r0, DZY + r0,
+                                              DT + TL::RY + r0, DZY + TL::RY + r0, BX, a.mu, a.kappa, a.inv24dy, Fd);
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) GL[m * TL::NFY + t] = F[m];
+                if constexpr (MODEL == DIM) UHB[t] = uh;
+            }
+            __syncthreads();
+            // ---- P6: y divergence of the own cell
+            {
+                const int fl = ty * BX + tx;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    const Real d = (GL[m * TL::NFY + fl + BX] - GL[m * TL::NFY + fl]) * idy;
+                    if constexpr (ACC_LDS) slot[m * NT] -= d;
+                    else accC[m] -= d;
+                }
+                if constexpr (MODEL == DIM) srcC += (UHB[fl + BX] - UHB[fl]) * idy;
+            }
+        }
+        // rotate carries
+        if constexpr (!ACC_LDS) {
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                accA[m] = accB[m];
+                accB[m] = accC[m];
+            }
         }
         srcA = srcB;
         srcB = srcC;
@@ -516,24 +529,24 @@ __global__ void __launch_bounds__(BX* BY) stage_kernel(const StageArgs<Real> a)
 #pragma unroll
         for (int q = 0; q < 5; q++)
 #pragma unroll
-            for (int f = 0; f < NW; f++) win[q][f] = win[q + 1][f];
+            for (int f = 0; f < NC; f++) win[q][f] = win[q + 1][f];
     }
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, int BX, int BY>
+template <typename Real, int MODEL, bool POS, int BX, int BY>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     using TL = Tile<Real, MODEL, BX, BY>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, BX, BY>,
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, BX, BY>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((stage_kernel<Real, MODEL, BX, BY>), dim3(g.nblocks), dim3(BX * BY), lds, st, args);
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, BX, BY>), dim3(g.nblocks), dim3(BX * BY), lds, st, args);
     return hipGetLastError();
 }
 
@@ -543,13 +556,20 @@ size_t stage_lds_bytes()
     return Tile<Real, MODEL, TILE_BX, TILE_BY>::bytes();
 }
 
+template <typename Real, int MODEL>
+static hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    if (args.positivity) return launch_tile<Real, MODEL, true, TILE_BX, TILE_BY>(args, g, st);
+    return launch_tile<Real, MODEL, false, TILE_BX, TILE_BY>(args, g, st);
+}
+
 template <typename Real>
 hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     switch (model) {
-    case EULER: return launch_tile<Real, EULER, TILE_BX, TILE_BY>(args, g, st);
-    case NS: return launch_tile<Real, NS, TILE_BX, TILE_BY>(args, g, st);
-    default: return launch_tile<Real, DIM, TILE_BX, TILE_BY>(args, g, st);
+    case EULER: return launch_model<Real, EULER>(args, g, st);
+    case NS: return launch_model<Real, NS>(args, g, st);
+    default: return launch_model<Real, DIM>(args, g, st);
     }
 }
 

@@ -22,7 +22,7 @@ ABI_VERSION = 1
 OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfvrk3.so")
+LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
 EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rk3_stage",
             "rk3_step", "compute_dt", "advance", "rhs_adjoint", "check_state", "last_error"]
