@@ -137,6 +137,15 @@ int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
 int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* Uk, void* Uout,
               double dt, const double* dt_dev, void* stream);
 
+/* Stage 3 of rk3_stage fused with the CFL reduction of its output:
+ * Uout = 1/3 Un + 2/3 Uk + 2/3 dt R(Uk) with dt = *dt_dev, then
+ * *dt_next = cfg->cfl * min(min_d dx_d / (|u_d| + c), (3/14) rho dx_min^2 / mu)
+ * over Uout (the time step of the next step, as compute_dt would give it,
+ * without another pass over the state).  dt_next may equal dt_dev.  ws: the
+ * workspace of workspace_bytes() (its scalar area holds the reduction). */
+int rk3_stage3_cfl(const fv_config* cfg, const void* Un, const void* Uk, void* Uout, const double* dt_dev,
+                   double* dt_next, void* ws, void* stream);
+
 /* One full TVD-RK3 step in place: U <- I_RK3(U, R, dt).  ws: workspace of
  * workspace_bytes(). */
 int rk3_step(const fv_config* cfg, void* U, double dt, void* ws, void* stream);

@@ -152,16 +152,20 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.inv24dy = (Real)(1.0 / (24.0 * c->dy));
     a.inv24dz = (Real)(1.0 / (24.0 * c->dz));
     a.mu = (Real)(c->model == FV_NS ? c->mu : 0.0);
+    const double hmin = fmin(c->dx, fmin(c->dy, c->dz));
+    a.kvisc = c->model == FV_NS ? (14.0 / 3.0) * c->mu / (hmin * hmin) : 0.0;
+    a.inv_max = nullptr;
     a.kappa = (Real)(c->model == FV_NS ? c->mu * c->gamma1 / ((c->gamma1 - 1.0) * c->prandtl) : 0.0);
     return a;
 }
 
 template <typename Real>
 int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt, const double* dt_dev,
-               hipStream_t st)
+               hipStream_t st, unsigned long long* inv_max)
 {
     fv::LaunchGeom g;
     fv::StageArgs<Real> a = stage_args<Real>(c, g);
+    a.inv_max = inv_max;
     a.Uk = (const Real*)Uk;
     a.Un = (const Real*)Un;
     a.out = (Real*)out;
@@ -174,10 +178,10 @@ int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, voi
 }
 
 int stage_dispatch(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt,
-                   const double* dt_dev, hipStream_t st)
+                   const double* dt_dev, hipStream_t st, unsigned long long* inv_max = nullptr)
 {
-    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st);
-    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st);
+    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max);
+    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max);
 }
 
 struct WsLayout {
@@ -298,12 +302,34 @@ int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* U
     return stage_dispatch(cfg, stage, Un, Uk, Uout, dt, dt_dev, (hipStream_t)stream);
 }
 
-static int step_impl(const fv_config* cfg, void* U, double dt, const double* dt_dev, const WsLayout& w, hipStream_t st)
+int rk3_stage3_cfl(const fv_config* cfg, const void* Un, const void* Uk, void* Uout, const double* dt_dev,
+                   double* dt_next, void* ws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(Un, "Un")) || (r = check_ptr(Uk, "Uk")) || (r = check_ptr(Uout, "Uout")) ||
+        (r = check_ptr(ws, "ws")))
+        return r;
+    if (!dt_dev || !dt_next) return fail(FV_ENULL, "dt_dev and dt_next are required");
+    if (Uk == Uout) return fail(FV_EINVAL, "Uout must not overlap Uk");
+    if (!(cfg->cfl > 0)) return fail(FV_EINVAL, "cfl must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    const WsLayout w = ws_layout(cfg, ws);
+    hipError_t e = fv::launch_reset_max(w.inv_max, st);
+    if (e != hipSuccess) return hip_fail(e, "rk3_stage3_cfl: reset");
+    if ((r = stage_dispatch(cfg, 3, Un, Uk, Uout, 0.0, dt_dev, st, w.inv_max))) return r;
+    e = fv::launch_dt_finish(w.inv_max, cfg->cfl, dt_next, nullptr, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "rk3_stage3_cfl: finish");
+    return FV_OK;
+}
+
+static int step_impl(const fv_config* cfg, void* U, double dt, const double* dt_dev, const WsLayout& w, hipStream_t st,
+                     unsigned long long* inv_max = nullptr)
 {
     int r;
     if ((r = stage_dispatch(cfg, 1, U, U, w.A, dt, dt_dev, st))) return r;
     if ((r = stage_dispatch(cfg, 2, U, w.A, w.B, dt, dt_dev, st))) return r;
-    return stage_dispatch(cfg, 3, U, w.B, U, dt, dt_dev, st);
+    return stage_dispatch(cfg, 3, U, w.B, U, dt, dt_dev, st, inv_max);
 }
 
 int rk3_step(const fv_config* cfg, void* U, double dt, void* ws, void* stream)
@@ -349,13 +375,19 @@ int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_
         hipError_t e = hipMemcpyAsync(w.t_acc, t_inout, sizeof(double), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "advance: t upload");
     }
+    if (cfl_mode && nsteps > 0) {
+        // dt of the first step from a full reduction; every later dt comes from the
+        // reduction fused into the previous step's third stage
+        hipError_t e = cfg->dtype == FV_F64
+                           ? fv::launch_dt<double>(a, (const double*)U, mu, cfg->cfl, w.inv_max, w.dt, nullptr, st)
+                           : fv::launch_dt<float>(a, (const float*)U, mu, cfg->cfl, w.inv_max, w.dt, nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "advance: dt");
+    }
     for (int n = 0; n < nsteps; n++) {
         if (cfl_mode) {
-            hipError_t e = cfg->dtype == FV_F64
-                               ? fv::launch_dt<double>(a, (const double*)U, mu, cfg->cfl, w.inv_max, w.dt, t_inout ? w.t_acc : nullptr, st)
-                               : fv::launch_dt<float>(a, (const float*)U, mu, cfg->cfl, w.inv_max, w.dt, t_inout ? w.t_acc : nullptr, st);
-            if (e != hipSuccess) return hip_fail(e, "advance: dt");
-            if ((r = step_impl(cfg, U, 0.0, w.dt, w, st))) return r;
+            if ((r = step_impl(cfg, U, 0.0, w.dt, w, st, w.inv_max))) return r;
+            hipError_t e = fv::launch_dt_finish(w.inv_max, cfg->cfl, w.dt, t_inout ? w.t_acc : nullptr, w.dt, st);
+            if (e != hipSuccess) return hip_fail(e, "advance: dt finish");
         } else {
             if ((r = step_impl(cfg, U, dt, nullptr, w, st))) return r;
         }

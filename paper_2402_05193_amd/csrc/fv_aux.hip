@@ -173,6 +173,11 @@ template hipError_t launch_init<double>(const AuxArgs&, int, const double*, int,
 template hipError_t launch_init<float>(const AuxArgs&, int, const double*, int, uint64_t, float*, hipStream_t);
 
 // ------------------------------------------------------------------ CFL time step
+__global__ void add_scalar_kernel_fwd(double* t_acc, const double* dt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t_acc += *dt;
+}
+
 __global__ void reset_u64_kernel(unsigned long long* p)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
@@ -183,10 +188,11 @@ __global__ void __launch_bounds__(AUX_THREADS) inv_dt_kernel(const AuxArgs a, co
                                                              unsigned long long* __restrict__ inv_max)
 {
     constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V;
-    __shared__ double red[AUX_THREADS];
-    const long long q = (long long)blockIdx.x * AUX_THREADS + threadIdx.x;
+    __shared__ double red[AUX_THREADS / 64];
     double v = 0.0;
-    if (q < a.ncell) {
+    const double hmin = fmin(a.dx, fmin(a.dy, a.dz));
+    for (long long q = (long long)blockIdx.x * AUX_THREADS + threadIdx.x; q < a.ncell;
+         q += (long long)gridDim.x * AUX_THREADS) {
         Real u[NC], w[NC];
 #pragma unroll
         for (int m = 0; m < NC; m++) u[m] = U[m * a.ncell + q];
@@ -196,30 +202,45 @@ __global__ void __launch_bounds__(AUX_THREADS) inv_dt_kernel(const AuxArgs a, co
         const double s0 = (fabs((double)w[V]) + c) / a.dx;
         const double s1 = (fabs((double)w[V + 1]) + c) / a.dy;
         const double s2 = (fabs((double)w[V + 2]) + c) / a.dz;
-        v = fmax(s0, fmax(s1, s2));
-        if (MODEL == NS && mu > 0.0) {
-            const double hmin = fmin(a.dx, fmin(a.dy, a.dz));
-            v = fmax(v, mu / (3.0 / 14.0 * rho * hmin * hmin));
-        }
-        if (!(v >= 0.0)) v = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf (dt -> 0)
+        double t = fmax(s0, fmax(s1, s2));
+        if (MODEL == NS && mu > 0.0) t = fmax(t, mu / (3.0 / 14.0 * rho * hmin * hmin));
+        if (!(t >= 0.0)) t = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf (dt -> 0)
+        v = fmax(v, t);
     }
-    red[threadIdx.x] = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = AUX_THREADS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int k = 1; k < AUX_THREADS / 64; k++) m = fmax(m, red[k]);
+        atomicMax(inv_max, (unsigned long long)__double_as_longlong(m));
     }
-    if (threadIdx.x == 0) atomicMax(inv_max, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-__global__ void dt_finish_kernel(const unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc)
+// t_acc += *dt_prev (optional); *dt_out = cfl / max; max = 0 for the next reduction
+__global__ void dt_finish_kernel(unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc,
+                                 const double* dt_prev)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (t_acc && dt_prev) *t_acc += *dt_prev;
         const double m = __longlong_as_double((long long)*inv_max);
-        const double dt = cfl / m;
-        *dt_out = dt;
-        if (t_acc) *t_acc += dt;
+        *dt_out = cfl / m;
+        *inv_max = 0ull;
     }
+}
+
+hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_u64_kernel, dim3(1), dim3(64), 0, st, inv_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_finish(unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc,
+                            const double* dt_prev, hipStream_t st)
+{
+    hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(64), 0, st, inv_max, cfl, dt_out, t_acc, dt_prev);
+    return hipGetLastError();
 }
 
 template <typename Real>
@@ -227,13 +248,17 @@ hipError_t launch_dt(const AuxArgs& a, const Real* U, double mu, double cfl, uns
                      double* dt_out, double* t_acc, hipStream_t st)
 {
     hipLaunchKernelGGL(reset_u64_kernel, dim3(1), dim3(64), 0, st, inv_max);
-    const int nb = aux_blocks(a.ncell);
+    long long nb = (a.ncell + AUX_THREADS - 1) / AUX_THREADS;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
     switch (a.model) {
     case EULER: hipLaunchKernelGGL((inv_dt_kernel<Real, EULER>), dim3(nb), dim3(AUX_THREADS), 0, st, a, U, mu, inv_max); break;
     case NS: hipLaunchKernelGGL((inv_dt_kernel<Real, NS>), dim3(nb), dim3(AUX_THREADS), 0, st, a, U, mu, inv_max); break;
     default: hipLaunchKernelGGL((inv_dt_kernel<Real, DIM>), dim3(nb), dim3(AUX_THREADS), 0, st, a, U, mu, inv_max); break;
     }
-    hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(64), 0, st, inv_max, cfl, dt_out, t_acc);
+    hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(64), 0, st, inv_max, cfl, dt_out, (double*)nullptr,
+                       (const double*)nullptr);
+    if (t_acc) hipLaunchKernelGGL(add_scalar_kernel_fwd, dim3(1), dim3(64), 0, st, t_acc, (const double*)dt_out);
     return hipGetLastError();
 }
 template hipError_t launch_dt<double>(const AuxArgs&, const double*, double, double, unsigned long long*, double*,

@@ -40,6 +40,10 @@ struct StageArgs {
     Real idx, idy, idz;
     Real inv12dx, inv12dy, inv12dz, inv24dx, inv24dy, inv24dz;
     Real mu, kappa;      // kappa = mu gamma / ((gamma-1) Pr)
+    // optional CFL reduction over the stage output (stage 3): max over cells of
+    // max_d (|u_d| + c)/dx_d and kvisc / rho, as the bit pattern of a double
+    unsigned long long* inv_max;
+    double kvisc;        // (14/3) mu / dx_min^2 (0 without viscosity)
 };
 
 struct LaunchGeom {
@@ -78,5 +82,10 @@ hipError_t launch_dt(const AuxArgs& a, const Real* U, double mu, double cfl, uns
 template <typename Real>
 hipError_t launch_check(const AuxArgs& a, const Real* U, long long* ws_words, hipStream_t st);
 hipError_t launch_add_scalar(double* t_acc, const double* dt, hipStream_t st);
+// *inv_max = 0
+hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st);
+// t_acc (optional) += *dt_prev;  *dt_out = cfl / max;  *inv_max = 0
+hipError_t launch_dt_finish(unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc,
+                            const double* dt_prev, hipStream_t st);
 
 }  // namespace fv

@@ -40,27 +40,43 @@ __device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* 
     if (fz) u[V + 2] = -u[V + 2];
 }
 
-// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3).
+// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3);
+// the written values are returned in `out` for the optional CFL reduction.
 template <typename Real, int NC>
-__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt)
+__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt, Real* out)
 {
     if (a.mode == 0) {
 #pragma unroll
-        for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = r[m];
+        for (int m = 0; m < NC; m++) out[m] = r[m];
     } else if (a.mode == 1) {
 #pragma unroll
-        for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = a.Uk[m * a.ncell + q] + dt * r[m];
+        for (int m = 0; m < NC; m++) out[m] = a.Uk[m * a.ncell + q] + dt * r[m];
     } else if (a.mode == 2) {
         const Real c1 = Real(0.75), c2 = Real(0.25);
 #pragma unroll
-        for (int m = 0; m < NC; m++)
-            a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+        for (int m = 0; m < NC; m++) out[m] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
     } else {
         const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
 #pragma unroll
-        for (int m = 0; m < NC; m++)
-            a.out[m * a.ncell + q] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+        for (int m = 0; m < NC; m++) out[m] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
     }
+#pragma unroll
+    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = out[m];
+}
+
+// Inverse CFL time step of a conservative state: max(max_d (|u_d| + c)/dx_d, kvisc/rho).
+template <typename Real, int MODEL>
+__device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Real* u)
+{
+    constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V;
+    Real w[NC];
+    cons_to_prim<Real, MODEL>(a.mat, u, w);
+    const Real ir = rcp(density<Real, MODEL>(w));
+    const Real c = sqrt_fast(rhoc2<Real, MODEL>(a.mat, w) * ir);
+    Real v = fmax((fabs(w[V]) + c) * a.idx, fmax((fabs(w[V + 1]) + c) * a.idy, (fabs(w[V + 2]) + c) * a.idz));
+    if constexpr (MODEL == NS) v = fmax(v, Real(a.kvisc) * ir);
+    const double d = (double)v;
+    return d >= 0.0 ? d : __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
 }
 
 // LDS geometry of one tile
@@ -168,6 +184,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
 #pragma unroll
         for (int c = 0; c < 4; c++) Dc[q][c] = 0;
 
+    double tmax = 0.0;  // CFL reduction over the finalised cells (stage 3)
     const Real idx = a.idx, idy = a.idy, idz = a.idz;
     const Real lamx = Real(2 * a.ndim) * dt * idx;
     const Real lamy = Real(2 * a.ndim) * dt * idy;
@@ -339,7 +356,9 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
                     }
                     if constexpr (MODEL == DIM) r[6] += win[1][6] * (srcA + (uh - uhzl) * idz);
-                    store_cell_impl<Real, NC>(a, q, r, dt);
+                    Real unew[NC];
+                    store_cell_impl<Real, NC>(a, q, r, dt, unew);
+                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL>(a, unew));
                 }
 #pragma unroll
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
@@ -530,6 +549,20 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
         for (int q = 0; q < 5; q++)
 #pragma unroll
             for (int f = 0; f < NC; f++) win[q][f] = win[q + 1][f];
+    }
+    if (a.inv_max) {
+        // block maximum of the inverse time step, one atomic per workgroup
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem_raw);
+        if ((tid & 63) == 0) red[tid >> 6] = tmax;
+        __syncthreads();
+        if (tid == 0) {
+            double m = red[0];
+            for (int k = 1; k < NT / 64; k++) m = fmax(m, red[k]);
+            atomicMax(a.inv_max, (unsigned long long)__double_as_longlong(m));
+        }
     }
 }
 

@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
 EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rk3_stage",
-            "rk3_step", "compute_dt", "advance", "rhs_adjoint", "check_state", "last_error"]
+            "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "check_state", "last_error"]
 
 
 class FVError(RuntimeError):
@@ -133,6 +133,7 @@ def lib():
         L.cons_to_prim.argtypes = [cp, vp, vp, vp]
         L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
         L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.rk3_stage3_cfl.argtypes = [cp, vp, vp, vp, vp, vp, vp, vp]
         L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
         L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
         L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
@@ -237,6 +238,17 @@ def rk3_stage(cfg: Config, stage: int, Un, Uk, Uout, dt: float = 0.0, dt_dev: to
     c = cfg.c_struct()
     _check(lib().rk3_stage(ctypes.byref(c), int(stage), _ptr(Un), _ptr(Uk), _ptr(Uout), float(dt), _ptr(dt_dev),
                            _stream(stream)))
+    return Uout
+
+
+def rk3_stage3_cfl(cfg: Config, Un, Uk, Uout, dt_dev: torch.Tensor, dt_next: torch.Tensor, ws: torch.Tensor,
+                   stream=None):
+    """Third stage fused with the CFL reduction of its output (writes dt_next on the device)."""
+    for t, n in ((Un, "Un"), (Uk, "Uk"), (Uout, "Uout")):
+        _state(cfg, t, n)
+    c = cfg.c_struct()
+    _check(lib().rk3_stage3_cfl(ctypes.byref(c), _ptr(Un), _ptr(Uk), _ptr(Uout), _ptr(dt_dev), _ptr(dt_next),
+                                _ptr(ws), _stream(stream)))
     return Uout
 
 

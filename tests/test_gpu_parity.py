@@ -255,6 +255,32 @@ def test_cfl_dt_and_advance_parity():
     assert np.all(comp_rel(host(Ud), Uo) <= 1e-12)
 
 
+def test_fused_stage3_cfl_matches_stage_and_oracle_dt():
+    case = WL.taylor_green(24, viscous=True, reynolds=50.0)
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    sc = solver_cfg(case, cfl=0.5)
+    Ud = dev(U)
+    ws = S.workspace(sc)
+    dtd = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    A = torch.empty_like(Ud)
+    B = torch.empty_like(Ud)
+    C = torch.empty_like(Ud)
+    S.rk3_stage(sc, 1, Ud, Ud, A, 0.0, dtd)
+    S.rk3_stage(sc, 2, Ud, A, B, 0.0, dtd)
+    S.rk3_stage(sc, 3, Ud, B, C, 0.0, dtd)
+    D = torch.empty_like(Ud)
+    nxt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.rk3_stage3_cfl(sc, Ud, B, D, dtd, nxt, ws)
+    assert torch.equal(C, D)
+    assert float(nxt.item()) == pytest.approx(O.compute_dt(oc, host(D), 0.5), rel=1e-14)
+    # in place (stage 3 overwrites U^n) and dt_next aliasing dt_dev
+    E = Ud.clone()
+    S.rk3_stage3_cfl(sc, E, B, E, dtd, dtd, ws)
+    assert torch.equal(E, C)
+    assert float(dtd.item()) == float(nxt.item())
+
+
 def test_check_state_reports_bad_cells():
     case = WL.taylor_green(16)
     sc = solver_cfg(case)
