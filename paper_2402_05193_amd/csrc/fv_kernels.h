@@ -14,8 +14,23 @@
 #ifndef TILE_BY
 #define TILE_BY 16
 #endif
+#ifndef TILE_NT
+#define TILE_NT 256
+#endif
 #ifndef WAVES_PER_EU
 #define WAVES_PER_EU 2
+#endif
+#ifndef FV_PREFETCH_RK
+#define FV_PREFETCH_RK 0
+#endif
+#ifndef FV_EARLY_HALO
+#define FV_EARLY_HALO 1
+#endif
+#ifndef FV_SPLIT_OWN_LOAD
+#define FV_SPLIT_OWN_LOAD 0
+#endif
+#ifndef FV_ROTATE_TASKS
+#define FV_ROTATE_TASKS 1
 #endif
 
 namespace fv {

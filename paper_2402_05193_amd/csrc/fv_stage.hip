@@ -27,11 +27,14 @@ namespace fv {
 
 template <typename Real>
 __device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* __restrict__ U, int gi, int gj,
-                                          int gk, Real* u, int nc, int V)
+                                          int gk, Real* u, int nc, int V, bool interior_xy)
 {
     bool fx = false, fy = false, fz = false;
-    const int i = map_index(gi, a.nx, a.bc[0], a.bc[1], fx);
-    const int j = map_index(gj, a.ny, a.bc[2], a.bc[3], fy);
+    int i = gi, j = gj;
+    if (!interior_xy) {
+        i = map_index(gi, a.nx, a.bc[0], a.bc[1], fx);
+        j = map_index(gj, a.ny, a.bc[2], a.bc[3], fy);
+    }
     const int k = map_index(gk, a.nz, a.bc[4], a.bc[5], fz);
     const long long q = ((long long)k * a.ny + j) * a.nx + i;
     for (int m = 0; m < nc; m++) u[m] = U[m * a.ncell + q];
@@ -40,25 +43,27 @@ __device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* 
     if (fz) u[V + 2] = -u[V + 2];
 }
 
-// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3);
-// the written values are returned in `out` for the optional CFL reduction.
+// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3)
+// from the preloaded U^(k) (uk) and U^n (un) of the cell; the written values
+// are returned in `out` for the optional CFL reduction.
 template <typename Real, int NC>
-__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt, Real* out)
+__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt,
+                                                const Real* uk, const Real* un, Real* out)
 {
     if (a.mode == 0) {
 #pragma unroll
         for (int m = 0; m < NC; m++) out[m] = r[m];
     } else if (a.mode == 1) {
 #pragma unroll
-        for (int m = 0; m < NC; m++) out[m] = a.Uk[m * a.ncell + q] + dt * r[m];
+        for (int m = 0; m < NC; m++) out[m] = uk[m] + dt * r[m];
     } else if (a.mode == 2) {
         const Real c1 = Real(0.75), c2 = Real(0.25);
 #pragma unroll
-        for (int m = 0; m < NC; m++) out[m] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+        for (int m = 0; m < NC; m++) out[m] = c1 * un[m] + c2 * uk[m] + (c2 * dt) * r[m];
     } else {
         const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
 #pragma unroll
-        for (int m = 0; m < NC; m++) out[m] = c1 * a.Un[m * a.ncell + q] + c2 * a.Uk[m * a.ncell + q] + (c2 * dt) * r[m];
+        for (int m = 0; m < NC; m++) out[m] = c1 * un[m] + c2 * uk[m] + (c2 * dt) * r[m];
     }
 #pragma unroll
     for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = out[m];
@@ -79,12 +84,14 @@ __device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Rea
     return d >= 0.0 ? d : __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
 }
 
-// LDS geometry of one tile
-template <typename Real, int MODEL, int BX, int BY>
+// LDS geometry of one tile of BX x BY cells worked on by NTH threads
+// (NTH >= BX * BY; the x/y task lists are sized to fit NTH in one round)
+template <typename Real, int MODEL, int BX, int BY, int NTH>
 struct Tile {
     static constexpr int NC = Layout<MODEL>::NC;
     static constexpr bool VISC = MODEL == NS;
-    static constexpr int NT = BX * BY;
+    static constexpr int NT = NTH;
+    static constexpr int NCELL = BX * BY;
     static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho) of the LDS plane
     static constexpr int PX = BX + 6, PY = BY + 6;  // plane with 3-cell halo
     static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
@@ -99,24 +106,26 @@ struct Tile {
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
     // five-equation model keeps them in registers instead (LDS budget)
     static constexpr bool ACC_LDS = MODEL != DIM;
-    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NT : 0;
+    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : 0;
     static constexpr size_t bytes()
     {
         return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE);
     }
 };
 
-template <typename Real, int MODEL, bool POS, int BX, int BY>
-__global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
+template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+__global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
 {
     using L = Layout<MODEL>;
-    using TL = Tile<Real, MODEL, BX, BY>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH>;
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
     constexpr bool ACC_LDS = TL::ACC_LDS;
     constexpr int NW = TL::NW, PX = TL::PX, PY = TL::PY;
-    constexpr int NT = BX * BY;
+    constexpr int NT = NTH;
+    constexpr int NCELL = BX * BY;
     constexpr int PLANE = PY * PX;
+    static_assert(NT >= NCELL && NT % 64 == 0, "threads must cover the tile");
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Real* Wp = reinterpret_cast<Real*>(smem_raw);
@@ -125,7 +134,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
     Real* DZX = UHB + TL::UH_SIZE;  // [2][BY][BX+4]   (u, w) d/dz, x-face region
     Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
     Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
-    Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NT]     x/y partial sums of R
+    Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NCELL]  x/y partial sums of R
 
     const Material<Real> mat = a.mat;
     const Tolerances<Real> tol = a.tol;
@@ -133,7 +142,11 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
     const Real dt = a.dt_dev ? Real(*a.dt_dev) : Real(a.dt);
 
     const int tid = threadIdx.x;
-    const int tx = tid % BX, ty = tid / BX;
+    const bool has_cell = tid < NCELL;  // threads beyond the tile only take x/y tasks
+    const int tx = tid % BX, ty = has_cell ? tid / BX : 0;
+    // task lists have a few tasks more than threads; the wave that takes the
+    // remainder rotates with the workgroup so co-resident groups spread it over SIMDs
+    const int rt = FV_ROTATE_TASKS ? (tid + 64 * (int)(blockIdx.x & 3)) % NT : tid;
     int b = blockIdx.x;
     // blocks of one tile column are consecutive; consecutive tiles share an XCD's L2
     const int chunk = b % a.nchunks;
@@ -144,14 +157,16 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
     const int z0 = chunk * a.zchunk;
     const int z1 = min(z0 + a.zchunk, a.nz);
     const int gx = x0 + tx, gy = y0 + ty;
-    const bool own_valid = gx < a.nx && gy < a.ny;
+    const bool own_valid = has_cell && gx < a.nx && gy < a.ny;
+    // the tile and its 3-cell x/y halo lie inside the domain: no boundary mapping in x, y
+    const bool interior_xy = x0 >= 3 && x0 + BX + 3 <= a.nx && y0 >= 3 && y0 + BY + 3 <= a.ny;
 
     auto wp = [&](int f, int i, int j) -> Real& { return Wp[f * PLANE + (j + 3) * PX + (i + 3)]; };
 
     // primitive state of an arbitrary (possibly outside) cell
     auto load_w = [&](int gi, int gj, int gk, Real* w) {
         Real u[NC];
-        load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V);
+        load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V, interior_xy);
         cons_to_prim<Real, MODEL>(mat, u, w);
     };
     auto stage_w = [&](int i, int j, const Real* w) {
@@ -164,7 +179,12 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
     Real win[6][NC];
     const int s_begin = VISC ? z0 - 2 : z0;
 #pragma unroll
-    for (int q = 0; q < 5; q++) load_w(gx, gy, s_begin - 3 + q, win[q]);
+    for (int q = 0; q < 5; q++) {
+        if (has_cell) load_w(gx, gy, s_begin - 3 + q, win[q]);
+        else
+#pragma unroll
+            for (int f = 0; f < NC; f++) win[q][f] = Real(1);
+    }
 
     Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
     Real accA[NC], accB[NC];  // x/y part of R of cells s-2, s-1 (register variant)
@@ -191,7 +211,13 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
     const Real lamz = Real(2 * a.ndim) * dt * idz;
 
     for (int s = s_begin; s <= z1 + 1; s++) {
-        load_w(gx, gy, s + 2, win[5]);
+        // own column, plane s+2: issued now, converted after the barrier below
+        Real raw[NC];
+        if (has_cell) load_cell<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, V, interior_xy);
+        else
+#pragma unroll
+            for (int f = 0; f < NC; f++) raw[f] = Real(1);
+        if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
         const bool xy = (s >= z0) && (s < z1);
         const bool need_plane = xy || (VISC && s >= z0 - 2);
         Real accC[NC];
@@ -200,45 +226,70 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
 #pragma unroll
         for (int m = 0; m < NC; m++) accC[m] = 0;
 
+        // U^(k), U^n of the cell finalised in this step (s-2), loaded early
+        Real pre_k[NC], pre_n[NC];
+        const bool fin = s >= z0 + 2 && own_valid;
+        if (FV_PREFETCH_RK && fin && a.mode != 0) {
+            const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                pre_k[m] = a.Uk[m * a.ncell + q];
+                pre_n[m] = a.mode >= 2 ? a.Un[m * a.ncell + q] : Real(0);
+            }
+        }
+
         if (need_plane) {
-            __syncthreads();
-            // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
-            stage_w(tx, ty, win[3]);
-            for (int h = tid; h < TL::NHALO; h += NT) {
-                int i, j;
+            // halo cell of this thread (at most one: NHALO <= NT), loaded before the barrier
+            static_assert(TL::NHALO <= NT, "one halo cell per thread");
+            int hi = 0, hj = 0;
+            Real hu[NC];
+            const bool has_halo = tid < TL::NHALO;
+            if (has_halo) {
+                const int h = tid;
                 if (h < 6 * BY) {
-                    j = h / 6;
+                    hj = h / 6;
                     const int k = h % 6;
-                    i = k < 3 ? k - 3 : BX + k - 3;
+                    hi = k < 3 ? k - 3 : BX + k - 3;
                 } else if (h < 6 * BY + 6 * BX) {
                     const int hh = h - 6 * BY;
-                    i = hh % BX;
+                    hi = hh % BX;
                     const int k = hh / BX;
-                    j = k < 3 ? k - 3 : BY + k - 3;
+                    hj = k < 3 ? k - 3 : BY + k - 3;
                 } else {
                     const int hh = h - 6 * BY - 6 * BX;  // 2-deep corners (viscous cross terms)
                     const int ci = hh & 3, cj = hh >> 2;
-                    i = ci < 2 ? ci - 2 : BX + ci - 2;
-                    j = cj < 2 ? cj - 2 : BY + cj - 2;
+                    hi = ci < 2 ? ci - 2 : BX + ci - 2;
+                    hj = cj < 2 ? cj - 2 : BY + cj - 2;
                 }
+                if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+            }
+            __syncthreads();
+            if (!FV_EARLY_HALO && has_halo) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+            if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
+            // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
+            if (has_cell) stage_w(tx, ty, win[3]);
+            if (has_halo) {
                 Real w[NC];
-                load_w(x0 + i, y0 + j, s, w);
-                stage_w(i, j, w);
+                cons_to_prim<Real, MODEL>(mat, hu, w);
+                stage_w(hi, hj, w);
             }
             if constexpr (VISC) {
                 if (xy) {
                     // d/dz of the velocity at plane s: own column from the window
                     const Real i12 = a.inv12dz;
-                    Real dz[3];
+                    if (has_cell) {
+                        Real dz[3];
 #pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        dz[c] = dcell(win[1][V + c], win[2][V + c], win[4][V + c], win[5][V + c], i12);
-                    DZX[0 * TL::RX + ty * (BX + 4) + tx + 2] = dz[0];
-                    DZX[1 * TL::RX + ty * (BX + 4) + tx + 2] = dz[2];
-                    DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
-                    DZY[1 * TL::RY + (ty + 2) * BX + tx] = dz[2];
-                    // halo columns of the viscous regions: from memory
-                    for (int h = tid; h < 4 * BY + 4 * BX; h += NT) {
+                        for (int c = 0; c < 3; c++)
+                            dz[c] = dcell(win[1][V + c], win[2][V + c], win[4][V + c], win[5][V + c], i12);
+                        DZX[0 * TL::RX + ty * (BX + 4) + tx + 2] = dz[0];
+                        DZX[1 * TL::RX + ty * (BX + 4) + tx + 2] = dz[2];
+                        DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
+                        DZY[1 * TL::RY + (ty + 2) * BX + tx] = dz[2];
+                    }
+                    // halo columns of the viscous regions: from memory, taken by the
+                    // highest-numbered threads (the regular halo ring uses the lowest)
+                    for (int h = NT - 1 - tid; h < 4 * BY + 4 * BX && h >= 0; h += NT) {
                         int i, j;
                         if (h < 4 * BY) {
                             j = h / 4;
@@ -256,8 +307,8 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
                         for (int k = 0; k < 4; k++) {
                             const int dk = k < 2 ? k - 2 : k - 1;
                             bool fx = false, fy = false, fz = false;
-                            const int ii = map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
-                            const int jj = map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
+                            const int ii = interior_xy ? x0 + i : map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
+                            const int jj = interior_xy ? y0 + j : map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
                             const int kk = map_index(s + dk, a.nz, a.bc[4], a.bc[5], fz);
                             const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
                             const Real ir = rcp(a.Uk[qq]);
@@ -279,7 +330,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
                 }
             }
             __syncthreads();
-            if constexpr (VISC) {
+            if (VISC && has_cell) {
                 // in-plane derivatives of the own column for the z faces
                 const Real i12x = a.inv12dx, i12y = a.inv12dy;
                 Dnew[0] = dcell(wp(V + 2, tx - 2, ty), wp(V + 2, tx - 1, ty), wp(V + 2, tx + 1, ty), wp(V + 2, tx + 2, ty), i12x);
@@ -289,8 +340,10 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
         }
 
+        if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
+
         // ---- z work of the own column (registers only): finalises cell s-2
-        if (s >= z0) {
+        if (has_cell && s >= z0) {
             // reconstruction of cell s-1 from W(s-3 .. s+1) = win[0..4]
             Real vm_new[NC], vp[NC];
 #pragma unroll
@@ -348,16 +401,23 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
                     const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
                     Real r[NC];
                     if constexpr (ACC_LDS) {
-                        const Real* slot = ACC + (s & 1) * NC * NT + tid;
+                        const Real* slot = ACC + (s & 1) * NC * NCELL + tid;
 #pragma unroll
-                        for (int m = 0; m < NC; m++) r[m] = slot[m * NT] - (F[m] - Fzl[m]) * idz;
+                        for (int m = 0; m < NC; m++) r[m] = slot[m * NCELL] - (F[m] - Fzl[m]) * idz;
                     } else {
 #pragma unroll
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
                     }
                     if constexpr (MODEL == DIM) r[6] += win[1][6] * (srcA + (uh - uhzl) * idz);
                     Real unew[NC];
-                    store_cell_impl<Real, NC>(a, q, r, dt, unew);
+                    if (!FV_PREFETCH_RK && a.mode != 0) {
+#pragma unroll
+                        for (int m = 0; m < NC; m++) {
+                            pre_k[m] = a.Uk[m * a.ncell + q];
+                            pre_n[m] = a.mode >= 2 ? a.Un[m * a.ncell + q] : Real(0);
+                        }
+                    }
+                    store_cell_impl<Real, NC>(a, q, r, dt, pre_k, pre_n, unew);
                     if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL>(a, unew));
                 }
 #pragma unroll
@@ -369,11 +429,11 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
         }
 
         if (xy) {
-            Real* slot = ACC + (s & 1) * NC * NT + tid;  // partial sums of cell s (ACC_LDS)
+            Real* slot = ACC + (s & 1) * NC * NCELL + tid;  // partial sums of cell s (ACC_LDS)
             // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
             Real* FL = FB;
             Real* FR = FB + NC * TL::NFX;
-            for (int t = tid; t < (BX + 2) * BY; t += NT) {
+            for (int t = rt; t < (BX + 2) * BY; t += NT) {
                 const int j = t / (BX + 2), i = t % (BX + 2) - 1;
 #pragma unroll
                 for (int m = 0; m < NC; m++) {
@@ -386,7 +446,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             if constexpr (VISC) {
                 const Real i12 = a.inv12dy;
-                for (int t = tid; t < TL::RX; t += NT) {
+                for (int t = rt; t < TL::RX; t += NT) {
                     const int j = t / (BX + 4), i = t % (BX + 4) - 2;
                     DT[t] = dcell(wp(V, i, j - 2), wp(V, i, j - 1), wp(V, i, j + 1), wp(V, i, j + 2), i12);
                     DT[TL::RX + t] =
@@ -395,7 +455,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             __syncthreads();
             // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
-            for (int t = tid; t < TL::NFX; t += NT) {
+            for (int t = rt; t < TL::NFX; t += NT) {
                 const int j = t / (BX + 1), f = t % (BX + 1);
                 Real wl[NC], wr[NC], F[NC], uh;
 #pragma unroll
@@ -438,12 +498,12 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             __syncthreads();
             // ---- P3: x divergence of the own cell
-            {
+            if (has_cell) {
                 const int fl = ty * (BX + 1) + tx;
 #pragma unroll
                 for (int m = 0; m < NC; m++) {
                     const Real v = -(FL[m * TL::NFX + fl + 1] - FL[m * TL::NFX + fl]) * idx;
-                    if constexpr (ACC_LDS) slot[m * NT] = v;
+                    if constexpr (ACC_LDS) slot[m * NCELL] = v;
                     else accC[m] = v;
                 }
                 if constexpr (MODEL == DIM) srcC = (UHB[fl + 1] - UHB[fl]) * idx;
@@ -452,7 +512,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
             Real* GL = FB;
             Real* GR = FB + NC * TL::NFY;
-            for (int t = tid; t < BX * (BY + 2); t += NT) {
+            for (int t = rt; t < BX * (BY + 2); t += NT) {
                 const int i = t % BX, j = t / BX - 1;
 #pragma unroll
                 for (int m = 0; m < NC; m++) {
@@ -465,7 +525,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             if constexpr (VISC) {
                 const Real i12 = a.inv12dx;
-                for (int t = tid; t < TL::RY; t += NT) {
+                for (int t = rt; t < TL::RY; t += NT) {
                     const int i = t % BX, j = t / BX - 2;
                     DT[t] = dcell(wp(V + 1, i - 2, j), wp(V + 1, i - 1, j), wp(V + 1, i + 1, j), wp(V + 1, i + 2, j), i12);
                     DT[TL::RY + t] = dcell(wp(V, i - 2, j), wp(V, i - 1, j), wp(V, i + 1, j), wp(V, i + 2, j), i12);
@@ -473,7 +533,7 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             __syncthreads();
             // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
-            for (int t = tid; t < TL::NFY; t += NT) {
+            for (int t = rt; t < TL::NFY; t += NT) {
                 const int i = t % BX, f = t / BX;
                 Real wl[NC], wr[NC], F[NC], uh;
 #pragma unroll
@@ -516,12 +576,12 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
             }
             __syncthreads();
             // ---- P6: y divergence of the own cell
-            {
+            if (has_cell) {
                 const int fl = ty * BX + tx;
 #pragma unroll
                 for (int m = 0; m < NC; m++) {
                     const Real d = (GL[m * TL::NFY + fl + BX] - GL[m * TL::NFY + fl]) * idy;
-                    if constexpr (ACC_LDS) slot[m * NT] -= d;
+                    if constexpr (ACC_LDS) slot[m * NCELL] -= d;
                     else accC[m] -= d;
                 }
                 if constexpr (MODEL == DIM) srcC += (UHB[fl + BX] - UHB[fl]) * idy;
@@ -567,33 +627,33 @@ __global__ void __launch_bounds__(BX* BY, WAVES_PER_EU) stage_kernel(const Stage
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, bool POS, int BX, int BY>
+template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    using TL = Tile<Real, MODEL, BX, BY>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, BX, BY>,
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, BX, BY, NTH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, BX, BY>), dim3(g.nblocks), dim3(BX * BY), lds, st, args);
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds, st, args);
     return hipGetLastError();
 }
 
 template <typename Real, int MODEL>
 size_t stage_lds_bytes()
 {
-    return Tile<Real, MODEL, TILE_BX, TILE_BY>::bytes();
+    return Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>::bytes();
 }
 
 template <typename Real, int MODEL>
 static hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    if (args.positivity) return launch_tile<Real, MODEL, true, TILE_BX, TILE_BY>(args, g, st);
-    return launch_tile<Real, MODEL, false, TILE_BX, TILE_BY>(args, g, st);
+    if (args.positivity) return launch_tile<Real, MODEL, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_tile<Real, MODEL, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
 template <typename Real>
