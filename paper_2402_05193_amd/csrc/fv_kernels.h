@@ -32,6 +32,13 @@
 #ifndef FV_ROTATE_TASKS
 #define FV_ROTATE_TASKS 1
 #endif
+// x/y reconstructions distributed over (component, cell) items instead of cells
+#ifndef FV_RECON_ITEMS
+#define FV_RECON_ITEMS 1
+#endif
+#ifndef FV_RECON_UNROLL
+#define FV_RECON_UNROLL 1
+#endif
 
 namespace fv {
 

@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
     constexpr bool ACC_LDS = TL::ACC_LDS;
-    constexpr int NW = TL::NW, PX = TL::PX, PY = TL::PY;
+    constexpr int PX = TL::PX, PY = TL::PY;
     constexpr int NT = NTH;
     constexpr int NCELL = BX * BY;
     constexpr int PLANE = PY * PX;
@@ -433,24 +433,40 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
             // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
             Real* FL = FB;
             Real* FR = FB + NC * TL::NFX;
-            for (int t = rt; t < (BX + 2) * BY; t += NT) {
-                const int j = t / (BX + 2), i = t % (BX + 2) - 1;
-#pragma unroll
-                for (int m = 0; m < NC; m++) {
+            if constexpr (FV_RECON_ITEMS) {
+                // one item = one component of one cell; consecutive lanes take consecutive cells
+                constexpr int NTX = (BX + 2) * BY;
+                auto item = [&](int it) {
+                    const int m = it / NTX, t = it - m * NTX;
+                    const int j = t / (BX + 2), i = t - j * (BX + 2) - 1;
+                    const Real* c = &wp(m, i, j);
                     Real vm, vp;
-                    weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
-                                weps, vm, vp);
+                    weno5z_pair(c[-2], c[-1], c[0], c[1], c[2], weps, vm, vp);
                     if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
                     if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                };
+#pragma unroll FV_RECON_UNROLL
+                for (int it = rt; it < NC * NTX; it += NT) item(it);
+            } else {
+                for (int t = rt; t < (BX + 2) * BY; t += NT) {
+                    const int j = t / (BX + 2), i = t % (BX + 2) - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
+                                    weps, vm, vp);
+                        if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
+                        if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                    }
                 }
             }
             if constexpr (VISC) {
+                // d/dy of u (c = 0) and v (c = 1) on the x-face region
                 const Real i12 = a.inv12dy;
-                for (int t = rt; t < TL::RX; t += NT) {
+                for (int it = rt; it < 2 * TL::RX; it += NT) {
+                    const int c = it >= TL::RX, t = it - c * TL::RX;
                     const int j = t / (BX + 4), i = t % (BX + 4) - 2;
-                    DT[t] = dcell(wp(V, i, j - 2), wp(V, i, j - 1), wp(V, i, j + 1), wp(V, i, j + 2), i12);
-                    DT[TL::RX + t] =
-                        dcell(wp(V + 1, i, j - 2), wp(V + 1, i, j - 1), wp(V + 1, i, j + 1), wp(V + 1, i, j + 2), i12);
+                    DT[it] = dcell(wp(V + c, i, j - 2), wp(V + c, i, j - 1), wp(V + c, i, j + 1), wp(V + c, i, j + 2), i12);
                 }
             }
             __syncthreads();
@@ -512,23 +528,40 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
             // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
             Real* GL = FB;
             Real* GR = FB + NC * TL::NFY;
-            for (int t = rt; t < BX * (BY + 2); t += NT) {
-                const int i = t % BX, j = t / BX - 1;
-#pragma unroll
-                for (int m = 0; m < NC; m++) {
+            if constexpr (FV_RECON_ITEMS) {
+                constexpr int NTY = BX * (BY + 2);
+                auto item = [&](int it) {
+                    const int m = it / NTY, t = it - m * NTY;
+                    const int jj = t / BX, i = t - jj * BX, j = jj - 1;
+                    const Real* c = &wp(m, i, j);
                     Real vm, vp;
-                    weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
-                                weps, vm, vp);
+                    weno5z_pair(c[-2 * PX], c[-PX], c[0], c[PX], c[2 * PX], weps, vm, vp);
                     if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
                     if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                };
+#pragma unroll FV_RECON_UNROLL
+                for (int it = rt; it < NC * NTY; it += NT) item(it);
+            } else {
+                for (int t = rt; t < BX * (BY + 2); t += NT) {
+                    const int i = t % BX, j = t / BX - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
+                                    weps, vm, vp);
+                        if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
+                        if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                    }
                 }
             }
             if constexpr (VISC) {
+                // d/dx of v (c = 0) and u (c = 1) on the y-face region
                 const Real i12 = a.inv12dx;
-                for (int t = rt; t < TL::RY; t += NT) {
+                for (int it = rt; it < 2 * TL::RY; it += NT) {
+                    const int c = it >= TL::RY, t = it - c * TL::RY;
                     const int i = t % BX, j = t / BX - 2;
-                    DT[t] = dcell(wp(V + 1, i - 2, j), wp(V + 1, i - 1, j), wp(V + 1, i + 1, j), wp(V + 1, i + 2, j), i12);
-                    DT[TL::RY + t] = dcell(wp(V, i - 2, j), wp(V, i - 1, j), wp(V, i + 1, j), wp(V, i + 2, j), i12);
+                    const int f = V + 1 - c;
+                    DT[it] = dcell(wp(f, i - 2, j), wp(f, i - 1, j), wp(f, i + 1, j), wp(f, i + 2, j), i12);
                 }
             }
             __syncthreads();
