@@ -74,6 +74,44 @@ def run_oracle_baseline(n: int, model: int) -> dict:
                       f"{el:.1f} s on {threads} threads"}
 
 
+def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: int = 2402) -> dict:
+    """Serving benchmark: a seeded Poisson stream of independent 3-D Riemann problems
+    (single- and two-phase, grids 64^3 .. 256x128x128, 50 RK3 steps each, FP32, CFL 0.5),
+    served by continuous batching (graph replay) and one request at a time."""
+    import numpy as np
+    import torch
+    from paper_2402_05193_amd import serving as SV
+    from paper_2402_05193_amd import solver as S
+    from paper_2402_05193_amd import workloads as WL
+
+    arrivals = WL.poisson_arrivals(n_req, rate, seed)
+    reqs = [WL.riemann_request(i, seed) for i in range(n_req)]
+    srv = SV.Server(pool_bytes=int(pool_gib * (1 << 30)), max_batch=max_batch, use_graph=True)
+    # warm-up: every kernel variant once on both paths (tiny grids)
+    warm = [SV.job_from_request(WL.riemann_request(i, seed + 1, grids=((16, 16, 16),), steps=2), 0.0)
+            for i in range(6)]
+    srv.run_batched(warm)
+    srv.run_sequential([SV.job_from_request(WL.riemann_request(i, seed + 1, grids=((16, 16, 16),), steps=2), 0.0)
+                        for i in range(6)])
+    out = {"workload": f"Poisson stream {rate:g} req/s of {n_req} planar 3-D Riemann problems "
+                       f"(Euler / five-equation air-helium, grids {list(WL.SERVING_GRIDS)}), "
+                       f"50 TVD-RK3 steps each at CFL 0.5, FP32, limiters on",
+           "arrival_rate_per_s": rate, "max_batch": max_batch, "pool_gib": pool_gib}
+    res = {}
+    for mode in ("batched", "sequential"):
+        jobs = [SV.job_from_request(r, a) for r, a in zip(reqs, arrivals)]
+        st = srv.run_batched(jobs) if mode == "batched" else srv.run_sequential(jobs)
+        res[mode] = st.summary()
+        print(f"[bench] serving {mode}: {json.dumps(res[mode])}", flush=True)
+    srv.close()
+    out.update(res)
+    out["throughput_ratio_batched_vs_sequential"] = (res["batched"]["cell_updates_per_s"] /
+                                                     res["sequential"]["cell_updates_per_s"])
+    out["p50_latency_s"] = res["batched"]["p50_latency_s"]
+    out["p99_latency_s"] = res["batched"]["p99_latency_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +123,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of known size first (for HBM counter scaling)")
+    ap.add_argument("--serve-requests", type=int, default=160,
+                    help="requests of the serving benchmark (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-batch", type=int, default=32)
+    ap.add_argument("--serve-pool-gib", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -205,6 +248,11 @@ def main():
         "wall_s": wall,
         "state_finite": finite,
     }
+    del U, A, B, ws
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        out["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_max_batch,
+                                     args.serve_pool_gib)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_oracle_baseline(args.n, model)
     print(json.dumps(out), flush=True)

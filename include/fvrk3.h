@@ -161,15 +161,81 @@ int compute_dt(const fv_config* cfg, const void* U, double* dt_dev, void* ws, vo
 int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws,
             void* stream);
 
-/* Vector-Jacobian product Ubar = (dR/dU)^T Rbar of the RHS.  Not built:
- * returns FV_EUNSUPPORTED. */
+/* Discrete adjoint (the reverse-mode derivative the paper takes by automatic
+ * differentiation of the solver, Sec. 6): the vector-Jacobian product
+ *   Ubar = (dR/dU)^T Rbar
+ * of rhs() at U, overwriting Ubar.  Covers the single-phase Euler model in
+ * FP64 with the positivity limiters off (other configurations return
+ * FV_EUNSUPPORTED); all boundary conditions.  Non-differentiable points take
+ * |x|' = sgn(x) with sgn(0) = 0, an even split at ties of min/max, and a zero
+ * derivative of the HLLC upwind switch.  Contributions are accumulated with
+ * atomic adds: reproducible to round-off, not bitwise.  ws is unused (may be
+ * NULL).  Ubar must not overlap U or Rbar. */
 int rhs_adjoint(const fv_config* cfg, const void* U, const void* Rbar, void* Ubar, void* ws,
                 void* stream);
+
+/* Bytes of workspace for rk3_step_adjoint: five state arrays. */
+int adjoint_workspace_bytes(const fv_config* cfg, size_t* out);
+
+/* Reverse sweep of one TVD-RK3 step at a fixed dt (Sec. 3.4): on entry Ubar
+ * holds the cotangent of U^{n+1} = I_RK3(U^n); on return the cotangent of U^n
+ * (dt is a constant of the step, not differentiated).  The stage states are
+ * recomputed from Un.  aws: adjoint_workspace_bytes() of device memory.  Same
+ * coverage as rhs_adjoint. */
+int rk3_step_adjoint(const fv_config* cfg, const void* Un, void* Ubar, double dt, void* aws, void* stream);
 
 /* Scan U for NaN/Inf and for cells outside the admissible set of Sec. 3.3
  * (rho > 0 and rho c^2 > 0; DIM: 0 <= a1 <= 1, a_k rho_k > 0).  Synchronises
  * the stream.  Returns the status also stored in out->status. */
 int check_state(const fv_config* cfg, const void* U, void* ws, fv_report* out, void* stream);
+
+/* Simulated time accumulated in a workspace by advance (CFL mode, when
+ * t_inout is given) or by the batched steps below, copied to the host double
+ * *t.  Synchronises the stream. */
+int workspace_time(const fv_config* cfg, const void* ws, double* t, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched time stepping of many independent problems (continuous batching).
+ *
+ * Each member is one problem: its fv_config, its state U and its workspace ws
+ * (workspace_bytes(cfg), exactly as for advance).  Members may differ in grid,
+ * model, precision, boundary conditions and parameters.  Every RK stage of a
+ * batched step is one launch per (model, precision, limiter) group, whose
+ * workgroups are spread over the group's members through a device table, so
+ * small problems fill the GPU together.  Time stepping is in CFL mode: each
+ * member keeps its own dt, recomputed on the device from its own state (the
+ * reduction fused into its third stage), and its own simulated time.  A
+ * member's arithmetic does not depend on the other members: its result is
+ * bitwise that of advance(cfg, U, nsteps, 0, ...) run alone.
+ * ------------------------------------------------------------------------- */
+typedef struct fv_batch fv_batch; /* opaque host-side handle */
+
+/* Device bytes of the request table of a batch of up to `capacity` members. */
+int batch_table_bytes(int32_t capacity, size_t* out);
+
+/* Create a batch handle.  table: caller-owned device buffer of at least
+ * batch_table_bytes(capacity) bytes, 256-byte aligned, used only by this
+ * handle.  The handle allocates pinned host staging memory (no device memory). */
+int batch_create(int32_t capacity, void* table, size_t table_bytes, fv_batch** out);
+
+/* Release the handle (waits for its pending table uploads). */
+int batch_destroy(fv_batch* b);
+
+/* Set the members: n <= capacity problems, arrays of n configs, states and
+ * workspaces.  fresh (optional, n flags): members whose time stepping starts
+ * now: their first dt is computed from U and their simulated time set to 0.
+ * The table upload is stream-ordered: work enqueued earlier still runs on the
+ * previous membership.  Invalidates a captured graph. */
+int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, void* const* ws, const int32_t* fresh,
+              void* stream);
+
+/* nsteps TVD-RK3 steps (Sec. 3.4) of every member, CFL mode. */
+int batch_step(fv_batch* b, int32_t nsteps, void* stream);
+
+/* As batch_step, through a HIP graph of nsteps steps captured on first use and
+ * replayed while the membership, nsteps and stream stay the same.  stream must
+ * not be the default (NULL) stream. */
+int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream);
 
 /* Thread-local message of the last failure ("" if none). */
 const char* last_error(void);

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvrk3.so")
-SOURCES = ["fv_stage.hip", "fv_aux.hip", "fv_api.hip"]
+SOURCES = ["fv_stage.hip", "fv_aux.hip", "fv_adjoint.hip", "fv_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -22,6 +22,10 @@ FLAGS = [
     "-shared",
     # keep the compiler from forming packed FP32 VALU operations
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fused multiply-adds only where one source expression has the a*b+c form:
+    # the arithmetic then follows the source, identical in every kernel that
+    # inlines the same device code (single-problem and batched launches)
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "../../include/fvrk3.h"
 #include "fv_kernels.h"
 
@@ -404,16 +406,84 @@ int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_
     return FV_OK;
 }
 
+static int adjoint_supported(const fv_config* cfg)
+{
+    if (cfg->model != FV_EULER) return fail(FV_EUNSUPPORTED, "the adjoint covers the single-phase Euler model");
+    if (cfg->dtype != FV_F64) return fail(FV_EUNSUPPORTED, "the adjoint is FP64");
+    if (positivity_on(cfg)) return fail(FV_EUNSUPPORTED, "the adjoint needs the positivity limiters off");
+    return FV_OK;
+}
+
+static fv::AdjointArgs adjoint_args(const fv_config* c)
+{
+    fv::AdjointArgs a;
+    memset(&a, 0, sizeof a);
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.ncell = (long long)c->nx * c->ny * c->nz;
+    for (int k = 0; k < 6; k++) a.bc[k] = c->bc[k];
+    a.mat = material<double>(c);
+    a.weps = c->weno_eps > 0 ? c->weno_eps : 1e-40;
+    a.idx = 1.0 / c->dx;
+    a.idy = 1.0 / c->dy;
+    a.idz = 1.0 / c->dz;
+    return a;
+}
+
 int rhs_adjoint(const fv_config* cfg, const void* U, const void* Rbar, void* Ubar, void* ws, void* stream)
 {
     int r = validate(cfg);
     if (r) return r;
-    (void)U;
-    (void)Rbar;
-    (void)Ubar;
+    if ((r = adjoint_supported(cfg))) return r;
     (void)ws;
-    (void)stream;
-    return fail(FV_EUNSUPPORTED, "rhs_adjoint is not built in this library");
+    if ((r = check_ptr(U, "U")) || (r = check_ptr(Rbar, "Rbar")) || (r = check_ptr(Ubar, "Ubar"))) return r;
+    if (Ubar == U || Ubar == Rbar) return fail(FV_EINVAL, "Ubar must not overlap U or Rbar");
+    hipError_t e = fv::launch_rhs_adjoint(adjoint_args(cfg), (const double*)U, (const double*)Rbar, (double*)Ubar,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rhs_adjoint");
+    return FV_OK;
+}
+
+int adjoint_workspace_bytes(const fv_config* cfg, size_t* out)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if (!out) return fail(FV_ENULL, "out is NULL");
+    *out = 5 * ((state_bytes(cfg) + 255) & ~(size_t)255);
+    return FV_OK;
+}
+
+int rk3_step_adjoint(const fv_config* cfg, const void* Un, void* Ubar, double dt, void* aws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = adjoint_supported(cfg))) return r;
+    if ((r = check_ptr(Un, "Un")) || (r = check_ptr(Ubar, "Ubar")) || (r = check_ptr(aws, "aws"))) return r;
+    if (!(dt > 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and > 0");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t sb = (state_bytes(cfg) + 255) & ~(size_t)255;
+    double* U1 = (double*)((char*)aws);
+    double* U2 = (double*)((char*)aws + sb);
+    double* G2 = (double*)((char*)aws + 2 * sb);
+    double* G1 = (double*)((char*)aws + 3 * sb);
+    double* T = (double*)((char*)aws + 4 * sb);
+    double* G3 = (double*)Ubar;
+    const long long n = 5ll * cfg->nx * cfg->ny * cfg->nz;
+    const fv::AdjointArgs a = adjoint_args(cfg);
+    // the stages of the forward step, recomputed from U^n
+    if ((r = stage_dispatch(cfg, 1, Un, Un, U1, dt, nullptr, st))) return r;
+    if ((r = stage_dispatch(cfg, 2, Un, U1, U2, dt, nullptr, st))) return r;
+    // reverse sweep of U1 = Un + dt R(Un); U2 = 3/4 Un + 1/4 U1 + 1/4 dt R(U1);
+    // U3 = 1/3 Un + 2/3 U2 + 2/3 dt R(U2)
+    hipError_t e = fv::launch_rhs_adjoint(a, U2, G3, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G2, n, 2.0 / 3.0, G3, 2.0 / 3.0 * dt, T, 0, nullptr, 0, nullptr, st);
+    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, U1, G2, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G1, n, 0.25, G2, 0.25 * dt, T, 0, nullptr, 0, nullptr, st);
+    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, (const double*)Un, G1, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G3, n, 1.0 / 3.0, G3, 0.75, G2, 1.0, G1, dt, T, st);
+    if (e != hipSuccess) return hip_fail(e, "rk3_step_adjoint");
+    return FV_OK;
 }
 
 int check_state(const fv_config* cfg, const void* U, void* ws, fv_report* out, void* stream)
@@ -440,5 +510,322 @@ int check_state(const fv_config* cfg, const void* U, void* ws, fv_report* out, v
 }
 
 const char* last_error(void) { return g_err; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+// A batch is a set of independent problems advanced together: every RK stage
+// is one launch per (model, precision, limiter) group whose workgroups are
+// spread over the group's problems through a device table.
+
+namespace {
+
+constexpr int MAX_GROUPS = 12;   // 3 models x 2 precisions x 2 limiter settings
+constexpr size_t TAB_ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + TAB_ALIGN - 1) & ~(TAB_ALIGN - 1); }
+
+struct BatchGroup {
+    int model, dtype, pos, count, nblocks;
+    size_t first_off, args_off[3];  // byte offsets in the device table
+};
+
+}  // namespace
+
+struct fv_batch {
+    int capacity = 0;
+    char* table = nullptr;  // device, caller-owned
+    size_t table_bytes = 0;
+    char* host[2] = {nullptr, nullptr};  // pinned staging of the table image
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int cur = 0;
+    int n = 0;
+    std::vector<BatchGroup> groups;
+    size_t scal_off = 0;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = 0;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+size_t table_bound(int capacity)
+{
+    const size_t per = 3 * sizeof(fv::StageArgs<double>) + sizeof(int) + sizeof(fv::BatchScalars);
+    // per group: the block prefix and three argument arrays, each padded to TAB_ALIGN
+    return (size_t)MAX_GROUPS * 4 * TAB_ALIGN + 2 * TAB_ALIGN + (size_t)capacity * per +
+           (size_t)(capacity + MAX_GROUPS) * sizeof(int) + sizeof(fv::BatchScalars) * 4;
+}
+
+template <typename Real>
+void fill_group_args(const fv_config* c, void* U, void* ws, char* img, const BatchGroup& g, int k, int first_block,
+                     int* nblocks)
+{
+    fv::LaunchGeom geo;
+    fv::StageArgs<Real> a = stage_args<Real>(c, geo);
+    const WsLayout w = ws_layout(c, ws);
+    a.dt_dev = w.dt;
+    a.dt = 0.0;
+    fv::StageArgs<Real>* st = nullptr;
+    for (int s = 0; s < 3; s++) {
+        fv::StageArgs<Real> b = a;
+        b.mode = s + 1;
+        b.Un = (const Real*)U;
+        b.Uk = (const Real*)(s == 0 ? U : s == 1 ? (void*)w.A : (void*)w.B);
+        b.out = (Real*)(s == 0 ? (void*)w.A : s == 1 ? (void*)w.B : U);
+        b.inv_max = s == 2 ? w.inv_max : nullptr;
+        st = reinterpret_cast<fv::StageArgs<Real>*>(img + g.args_off[s]);
+        st[k] = b;
+    }
+    reinterpret_cast<int*>(img + g.first_off)[k] = first_block;
+    *nblocks = geo.nblocks;
+}
+
+int batch_launch_steps(fv_batch* b, int nsteps, hipStream_t st)
+{
+    const fv::BatchScalars* scal = reinterpret_cast<const fv::BatchScalars*>(b->table + b->scal_off);
+    for (int k = 0; k < nsteps; k++) {
+        for (int s = 0; s < 3; s++) {
+            for (const BatchGroup& g : b->groups) {
+                const int* first = reinterpret_cast<const int*>(b->table + g.first_off);
+                hipError_t e =
+                    g.dtype == FV_F64
+                        ? fv::launch_batch_stage<double>(g.model, g.pos != 0,
+                                                         reinterpret_cast<const fv::StageArgs<double>*>(b->table + g.args_off[s]),
+                                                         first, g.count, g.nblocks, st)
+                        : fv::launch_batch_stage<float>(g.model, g.pos != 0,
+                                                        reinterpret_cast<const fv::StageArgs<float>*>(b->table + g.args_off[s]),
+                                                        first, g.count, g.nblocks, st);
+                if (e != hipSuccess) return hip_fail(e, "batch stage launch");
+            }
+        }
+        hipError_t e = fv::launch_batch_dt_finish(scal, b->n, st);
+        if (e != hipSuccess) return hip_fail(e, "batch dt finish");
+    }
+    return FV_OK;
+}
+
+void drop_graph(fv_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->graph_steps = 0;
+    b->graph_stream = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int batch_table_bytes(int32_t capacity, size_t* out)
+{
+    if (!out) return fail(FV_ENULL, "out is NULL");
+    if (capacity < 1 || capacity > (1 << 20)) return fail(FV_EINVAL, "capacity %d out of range", capacity);
+    *out = table_bound(capacity);
+    return FV_OK;
+}
+
+int batch_create(int32_t capacity, void* table, size_t table_bytes, fv_batch** out)
+{
+    if (!out) return fail(FV_ENULL, "out is NULL");
+    *out = nullptr;
+    if (capacity < 1 || capacity > (1 << 20)) return fail(FV_EINVAL, "capacity %d out of range", capacity);
+    int r = check_ptr(table, "table");
+    if (r) return r;
+    if ((uintptr_t)table % TAB_ALIGN) return fail(FV_EALIGN, "table must be 256-byte aligned");
+    if (table_bytes < table_bound(capacity))
+        return fail(FV_EINVAL, "table of %zu bytes is smaller than batch_table_bytes (%zu)", table_bytes,
+                    table_bound(capacity));
+    fv_batch* b = new fv_batch;
+    b->capacity = capacity;
+    b->table = (char*)table;
+    b->table_bytes = table_bytes;
+    for (int k = 0; k < 2; k++) {
+        hipError_t e = hipHostMalloc((void**)&b->host[k], table_bound(capacity), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            batch_destroy(b);
+            return hip_fail(e, "batch_create");
+        }
+    }
+    *out = b;
+    return FV_OK;
+}
+
+int batch_destroy(fv_batch* b)
+{
+    if (!b) return FV_OK;
+    drop_graph(b);
+    for (int k = 0; k < 2; k++) {
+        if (b->copied[k]) {
+            if (b->pending[k]) (void)hipEventSynchronize(b->copied[k]);
+            (void)hipEventDestroy(b->copied[k]);
+        }
+        if (b->host[k]) (void)hipHostFree(b->host[k]);
+    }
+    delete b;
+    return FV_OK;
+}
+
+int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, void* const* ws, const int32_t* fresh,
+              void* stream)
+{
+    if (!b) return fail(FV_ENULL, "batch is NULL");
+    if (n < 0 || n > b->capacity) return fail(FV_EINVAL, "n = %d outside 0 .. capacity %d", n, b->capacity);
+    if (n > 0 && (!cfgs || !U || !ws)) return fail(FV_ENULL, "cfgs, U and ws are required");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < n; i++) {
+        int r = validate(&cfgs[i]);
+        if (r) return fail(r, "member %d: %s", i, last_error());
+        if ((r = check_ptr(U[i], "U")) || (r = check_ptr(ws[i], "ws"))) return fail(r, "member %d: %s", i, last_error());
+        if (!(cfgs[i].cfl > 0)) return fail(FV_EINVAL, "member %d: cfl must be > 0", i);
+    }
+    // groups in order of first appearance; members keep their order inside a group
+    std::vector<BatchGroup> groups;
+    std::vector<int> gid(n);
+    for (int i = 0; i < n; i++) {
+        const int pos = positivity_on(&cfgs[i]) ? 1 : 0;
+        int g = 0;
+        for (; g < (int)groups.size(); g++)
+            if (groups[g].model == cfgs[i].model && groups[g].dtype == cfgs[i].dtype && groups[g].pos == pos) break;
+        if (g == (int)groups.size()) {
+            BatchGroup ng;
+            memset(&ng, 0, sizeof ng);
+            ng.model = cfgs[i].model;
+            ng.dtype = cfgs[i].dtype;
+            ng.pos = pos;
+            groups.push_back(ng);
+        }
+        groups[g].count++;
+        gid[i] = g;
+    }
+    size_t off = 0;
+    for (BatchGroup& g : groups) {
+        const size_t as = g.dtype == FV_F64 ? sizeof(fv::StageArgs<double>) : sizeof(fv::StageArgs<float>);
+        g.first_off = off;
+        off = align_up(off + sizeof(int) * (size_t)(g.count + 1));
+        for (int s = 0; s < 3; s++) {
+            g.args_off[s] = off;
+            off = align_up(off + as * (size_t)g.count);
+        }
+    }
+    const size_t scal_off = off;
+    off = align_up(off + sizeof(fv::BatchScalars) * (size_t)(n > 0 ? n : 1));
+    if (off > b->table_bytes || off > table_bound(b->capacity))
+        return fail(FV_EINVAL, "batch table too small (%zu > %zu)", off, b->table_bytes);
+
+    // the staging buffer may still feed an earlier copy
+    const int k = b->cur;
+    if (b->pending[k]) {
+        hipError_t e = hipEventSynchronize(b->copied[k]);
+        if (e != hipSuccess) return hip_fail(e, "batch_set: staging wait");
+        b->pending[k] = false;
+    }
+    char* img = b->host[k];
+    memset(img, 0, off);
+    std::vector<int> slot(groups.size(), 0), first(groups.size(), 0);
+    fv::BatchScalars* sc = reinterpret_cast<fv::BatchScalars*>(img + scal_off);
+    for (int i = 0; i < n; i++) {
+        BatchGroup& g = groups[gid[i]];
+        int nb = 0;
+        if (g.dtype == FV_F64) fill_group_args<double>(&cfgs[i], U[i], ws[i], img, g, slot[gid[i]], first[gid[i]], &nb);
+        else fill_group_args<float>(&cfgs[i], U[i], ws[i], img, g, slot[gid[i]], first[gid[i]], &nb);
+        slot[gid[i]]++;
+        first[gid[i]] += nb;
+        const WsLayout w = ws_layout(&cfgs[i], ws[i]);
+        sc[i].inv_max = w.inv_max;
+        sc[i].dt = w.dt;
+        sc[i].t_acc = w.t_acc;
+        sc[i].cfl = cfgs[i].cfl;
+    }
+    for (size_t g = 0; g < groups.size(); g++) {
+        reinterpret_cast<int*>(img + groups[g].first_off)[groups[g].count] = first[g];
+        groups[g].nblocks = first[g];
+    }
+    // kernel attributes before any capture
+    for (const BatchGroup& g : groups) {
+        hipError_t e = g.dtype == FV_F64 ? fv::launch_batch_stage<double>(g.model, g.pos != 0, nullptr, nullptr, 0, 0, st)
+                                         : fv::launch_batch_stage<float>(g.model, g.pos != 0, nullptr, nullptr, 0, 0, st);
+        if (e != hipSuccess) return hip_fail(e, "batch_set: kernel attributes");
+    }
+    hipError_t e = hipMemcpyAsync(b->table, img, off, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(b->copied[k], st);
+    if (e != hipSuccess) return hip_fail(e, "batch_set: table upload");
+    b->pending[k] = true;
+    b->cur = 1 - k;
+    // new members: first dt from a full reduction, simulated time 0
+    for (int i = 0; i < n; i++) {
+        if (!fresh || !fresh[i]) continue;
+        const fv_config* c = &cfgs[i];
+        const WsLayout w = ws_layout(c, ws[i]);
+        const fv::AuxArgs a = aux_args(c);
+        const double mu = c->model == FV_NS ? c->mu : 0.0;
+        e = c->dtype == FV_F64 ? fv::launch_dt<double>(a, (const double*)U[i], mu, c->cfl, w.inv_max, w.dt, nullptr, st)
+                               : fv::launch_dt<float>(a, (const float*)U[i], mu, c->cfl, w.inv_max, w.dt, nullptr, st);
+        if (e == hipSuccess) e = fv::launch_reset_max((unsigned long long*)w.t_acc, st);
+        if (e != hipSuccess) return hip_fail(e, "batch_set: first dt");
+    }
+    drop_graph(b);
+    b->groups = groups;
+    b->n = n;
+    b->scal_off = scal_off;
+    return FV_OK;
+}
+
+int batch_step(fv_batch* b, int32_t nsteps, void* stream)
+{
+    if (!b) return fail(FV_ENULL, "batch is NULL");
+    if (nsteps < 0) return fail(FV_EINVAL, "nsteps must be >= 0");
+    if (b->n == 0) return FV_OK;
+    return batch_launch_steps(b, nsteps, (hipStream_t)stream);
+}
+
+int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream)
+{
+    if (!b) return fail(FV_ENULL, "batch is NULL");
+    if (nsteps < 1) return fail(FV_EINVAL, "nsteps must be >= 1");
+    if (!stream) return fail(FV_EINVAL, "graph capture needs a non-default stream");
+    if (b->n == 0) return FV_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (!b->exec || b->graph_steps != nsteps || b->graph_stream != st) {
+        drop_graph(b);
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "batch_step_graph: begin capture");
+        const int r = batch_launch_steps(b, nsteps, st);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(st, &graph);
+        if (r) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) return hip_fail(e, "batch_step_graph: end capture");
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(e, "batch_step_graph: instantiate");
+        }
+        b->graph_steps = nsteps;
+        b->graph_stream = st;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "batch_step_graph: launch");
+    return FV_OK;
+}
+
+int workspace_time(const fv_config* cfg, const void* ws, double* t, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(ws, "ws"))) return r;
+    if (!t) return fail(FV_ENULL, "t is NULL");
+    const WsLayout w = ws_layout(cfg, (void*)ws);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(t, w.t_acc, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "workspace_time");
+    return FV_OK;
+}
 
 }  // extern "C"

@@ -230,6 +230,25 @@ __global__ void dt_finish_kernel(unsigned long long* inv_max, double cfl, double
     }
 }
 
+__global__ void batch_dt_finish_kernel(const BatchScalars* __restrict__ s, int n)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        const BatchScalars b = s[r];
+        *b.t_acc += *b.dt;
+        const double m = __longlong_as_double((long long)*b.inv_max);
+        *b.dt = b.cfl / m;
+        *b.inv_max = 0ull;
+    }
+}
+
+hipError_t launch_batch_dt_finish(const BatchScalars* s, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_dt_finish_kernel, dim3((n + 63) / 64), dim3(64), 0, st, s, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st)
 {
     hipLaunchKernelGGL(reset_u64_kernel, dim3(1), dim3(64), 0, st, inv_max);

@@ -36,6 +36,9 @@
 #ifndef FV_RECON_ITEMS
 #define FV_RECON_ITEMS 1
 #endif
+#ifndef FV_KERNARG_INPLACE
+#define FV_KERNARG_INPLACE 0
+#endif
 #ifndef FV_RECON_UNROLL
 #define FV_RECON_UNROLL 1
 #endif
@@ -78,6 +81,24 @@ hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom
 template <typename Real, int MODEL>
 size_t stage_lds_bytes();
 
+// Fused stage over n independent problems of one model / precision / limiter
+// setting: args[r] describes problem r, whose workgroups are first[r] ..
+// first[r+1]-1 (device arrays); nblocks = first[n].  nblocks 0 only prepares
+// the kernel's attributes (call before stream capture).
+template <typename Real>
+hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
+                              hipStream_t st);
+
+// Per-problem scalars of a batch in CFL mode.
+struct BatchScalars {
+    unsigned long long* inv_max;  // stage-3 reduction target
+    double* dt;                   // time step of the next step
+    double* t_acc;                // simulated time
+    double cfl;
+};
+// for every r < n: t_acc += dt; dt = cfl / inv_max; inv_max = 0
+hipError_t launch_batch_dt_finish(const BatchScalars* s, int n, hipStream_t st);
+
 // Point-wise / reduction kernels (fv_aux.hip)
 struct AuxArgs {
     int model, nx, ny, nz;
@@ -109,5 +130,21 @@ hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st);
 // t_acc (optional) += *dt_prev;  *dt_out = cfl / max;  *inv_max = 0
 hipError_t launch_dt_finish(unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc,
                             const double* dt_prev, hipStream_t st);
+
+// Discrete adjoint of the single-phase Euler right-hand side (fv_adjoint.hip).
+struct AdjointArgs {
+    int nx, ny, nz;
+    long long ncell;
+    int bc[6];
+    Material<double> mat;
+    double weps;
+    double idx, idy, idz;
+    double ih;  // 1/h of the direction being processed (set by the launcher)
+};
+// Ubar = (dR/dU)^T Rbar (overwritten), FP64
+hipError_t launch_rhs_adjoint(const AdjointArgs& a, const double* U, const double* Rbar, double* Ubar, hipStream_t st);
+// out = c0 x0 + c1 x1 + c2 x2 + c3 x3 over n values (null x1..x3 skipped; out may alias)
+hipError_t launch_lincomb(double* out, long long n, double c0, const double* x0, double c1, const double* x1, double c2,
+                          const double* x2, double c3, const double* x3, hipStream_t st);
 
 }  // namespace fv

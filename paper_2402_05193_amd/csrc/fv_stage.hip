@@ -113,8 +113,9 @@ struct Tile {
     }
 };
 
+// One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
 template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
-__global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
+__device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
 {
     using L = Layout<MODEL>;
     using TL = Tile<Real, MODEL, BX, BY, NTH>;
@@ -127,7 +128,6 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
     constexpr int PLANE = PY * PX;
     static_assert(NT >= NCELL && NT % 64 == 0, "threads must cover the tile");
 
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     Real* Wp = reinterpret_cast<Real*>(smem_raw);
     Real* FB = Wp + TL::WP_SIZE;
     Real* UHB = FB + TL::FB_SIZE;
@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
     const int tx = tid % BX, ty = has_cell ? tid / BX : 0;
     // task lists have a few tasks more than threads; the wave that takes the
     // remainder rotates with the workgroup so co-resident groups spread it over SIMDs
-    const int rt = FV_ROTATE_TASKS ? (tid + 64 * (int)(blockIdx.x & 3)) % NT : tid;
-    int b = blockIdx.x;
+    const int rt = FV_ROTATE_TASKS ? (tid + 64 * (bid & 3)) % NT : tid;
+    int b = bid;
     // blocks of one tile column are consecutive; consecutive tiles share an XCD's L2
     const int chunk = b % a.nchunks;
     b /= a.nchunks;
@@ -659,6 +659,38 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
     }
 }
 
+template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+__global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+#if FV_KERNARG_INPLACE
+    // the argument block read in place from the kernel-argument segment
+    const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
+    stage_body<Real, MODEL, POS, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
+#else
+    stage_body<Real, MODEL, POS, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
+#endif
+}
+
+// Many independent problems in one launch: the workgroups of problem r are
+// first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
+// and limiter setting for every problem of the launch).
+template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+__global__ void __launch_bounds__(NTH, WAVES_PER_EU)
+    batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first, const int n)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = (int)blockIdx.x;
+    if (b >= first[n]) return;
+    int lo = 0, hi = n - 1;  // last r with first[r] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    stage_body<Real, MODEL, POS, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
@@ -688,6 +720,43 @@ static hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g,
     if (args.positivity) return launch_tile<Real, MODEL, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
     return launch_tile<Real, MODEL, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
+
+template <typename Real, int MODEL, bool POS>
+static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, int n, int nblocks, hipStream_t st)
+{
+    using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>;
+    const size_t lds = TL::bytes();
+    auto* k = batch_stage_kernel<Real, MODEL, POS, TILE_BX, TILE_BY, TILE_NT>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (nblocks <= 0) return hipSuccess;  // attribute set-up only
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(TILE_NT), lds, st, args, first, n);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
+                              hipStream_t st)
+{
+    switch (model) {
+    case EULER:
+        return pos ? launch_batch_tile<Real, EULER, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, EULER, false>(args, first, n, nblocks, st);
+    case NS:
+        return pos ? launch_batch_tile<Real, NS, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, NS, false>(args, first, n, nblocks, st);
+    default:
+        return pos ? launch_batch_tile<Real, DIM, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, DIM, false>(args, first, n, nblocks, st);
+    }
+}
+
+template hipError_t launch_batch_stage<double>(int, bool, const StageArgs<double>*, const int*, int, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(int, bool, const StageArgs<float>*, const int*, int, int, hipStream_t);
 
 template <typename Real>
 hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)

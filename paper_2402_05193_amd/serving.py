@@ -1,0 +1,311 @@
+"""Continuous batching of independent finite-volume solves on one GPU.
+
+A stream of requests (each: one problem and a number of TVD-RK3 steps) is
+served from one device memory arena.  A request is admitted when a batch slot
+and arena space for its state and workspace are free; its initial condition is
+written in place and it joins the running batch at the next step boundary.
+Every step advances all admitted requests together through the batched entry
+points of the library (one launch per RK stage and model group, optionally
+replayed from a captured HIP graph); a request leaves the batch after its last
+step and its memory returns to the arena once the device has finished with it.
+
+``run_sequential`` serves the same stream one request at a time with the
+single-problem ``advance`` call, for comparison.  Latency of a request is the
+time from its arrival to the completion, on the device, of its last step (HIP
+event timestamps against a reference event recorded at the start).
+
+Scheduling and memory bookkeeping live on the host; every step of the solve
+runs in the HIP library.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import solver as S
+
+ALIGN = 256
+
+
+def _align(n: int) -> int:
+    return (int(n) + ALIGN - 1) // ALIGN * ALIGN
+
+
+class FirstFit:
+    """First-fit allocator of byte ranges of one arena (offsets and sizes 256-byte aligned)."""
+
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes) // ALIGN * ALIGN
+        self.free = [(0, self.size)]  # sorted, coalesced (offset, length)
+
+    def alloc(self, n: int):
+        n = _align(n)
+        for i, (o, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + n, ln - n)
+                return o
+        return None
+
+    def release(self, off: int, n: int):
+        n = _align(n)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        if i > 0:
+            po, pl = self.free[i - 1]
+            if po + pl > off:
+                raise ValueError("double free or overlap")
+        if i < len(self.free) and off + n > self.free[i][0]:
+            raise ValueError("double free or overlap")
+        self.free.insert(i, (off, n))
+        # coalesce with the neighbours
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+
+    @property
+    def available(self) -> int:
+        return sum(ln for _, ln in self.free)
+
+
+@dataclass
+class Job:
+    """A request in flight: its problem, arrival time and, once admitted, its memory."""
+    index: int
+    cfg: S.Config
+    case_id: int
+    params: list
+    steps: int
+    arrival: float
+    seed: int = 0
+    nbytes: int = 0
+    off: int = -1
+    U: torch.Tensor | None = None
+    ws: torch.Tensor | None = None
+    steps_done: int = 0
+    admitted: float | None = None
+    finish: float | None = None
+    result: torch.Tensor | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+    @property
+    def cell_updates(self) -> int:
+        return self.cfg.ncells * 3 * self.steps
+
+
+def job_from_request(req, arrival: float, dtype: int = S.F32, cfl: float = 0.5) -> Job:
+    cfg = S.Config(**req.cfg_kwargs(), dtype=dtype, cfl=cfl)
+    return Job(index=req.index, cfg=cfg, case_id=S.CASE_RIEMANN, params=req.riemann_params(), steps=req.steps,
+               arrival=float(arrival))
+
+
+@dataclass
+class RunStats:
+    mode: str
+    n: int
+    makespan: float
+    latencies: np.ndarray = field(repr=False)
+    cell_updates: int = 0
+    max_batch_seen: int = 0
+    steps_launched: int = 0
+
+    def summary(self) -> dict:
+        lat = self.latencies
+        return {"mode": self.mode, "requests": self.n, "makespan_s": self.makespan,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "mean_latency_s": float(lat.mean()), "requests_per_s": self.n / self.makespan,
+                "cell_updates_per_s": self.cell_updates / self.makespan,
+                "max_batch": self.max_batch_seen, "batched_steps": self.steps_launched}
+
+
+class Server:
+    """Owns the arena, the batch handle and the stream the solves run on."""
+
+    def __init__(self, pool_bytes: int = 12 << 30, max_batch: int = 32, device="cuda", use_graph: bool = True,
+                 max_inflight: int = 2):
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)  # default priority
+        self.arena = torch.empty(int(pool_bytes) // ALIGN * ALIGN, dtype=torch.uint8, device=self.device)
+        self.heap = FirstFit(self.arena.numel())
+        self.max_batch = int(max_batch)
+        self.batch = S.Batch(self.max_batch, self.device)
+        self.use_graph = use_graph
+        self.max_inflight = max_inflight
+
+    # ---------------------------------------------------------------- memory
+    @staticmethod
+    def job_bytes(cfg: S.Config) -> int:
+        es = 8 if cfg.dtype == S.F64 else 4
+        return _align(cfg.ncomp * cfg.ncells * es) + _align(S.workspace_bytes(cfg))
+
+    def _place(self, job: Job) -> bool:
+        job.nbytes = self.job_bytes(job.cfg)
+        off = self.heap.alloc(job.nbytes)
+        if off is None:
+            return False
+        job.off = off
+        sb = _align(job.cfg.ncomp * job.cfg.ncells * (8 if job.cfg.dtype == S.F64 else 4))
+        U = self.arena.narrow(0, off, job.cfg.ncomp * job.cfg.ncells * (8 if job.cfg.dtype == S.F64 else 4))
+        job.U = U.view(job.cfg.torch_dtype).view(job.cfg.shape)
+        job.ws = self.arena.narrow(0, off + sb, S.workspace_bytes(job.cfg))
+        return True
+
+    def _free(self, job: Job):
+        self.heap.release(job.off, job.nbytes)
+        job.U = job.ws = None
+        job.off = -1
+
+    def _init(self, job: Job):
+        S.init_state(job.cfg, job.case_id, job.params, job.U, seed=job.seed, stream=self.stream)
+
+    def _finish_job(self, job: Job, keep_results: bool):
+        if keep_results:
+            with torch.cuda.stream(self.stream):
+                job.result = job.U.clone()
+
+    # ------------------------------------------------------------------ runs
+    def _start_clock(self):
+        torch.cuda.synchronize(self.device)
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record(self.stream)
+        ref.synchronize()
+        return ref, time.perf_counter()
+
+    def run_batched(self, jobs: list[Job], keep_results: bool = False) -> RunStats:
+        """Serve the jobs (sorted by arrival) with continuous batching."""
+        jobs = sorted(jobs, key=lambda j: j.arrival)
+        n = len(jobs)
+        queue: deque[Job] = deque()
+        active: list[Job] = []
+        fresh: set[int] = set()
+        inflight: deque = deque()
+        changed = False
+        nxt = done = 0
+        max_seen = steps = 0
+        ref, t0 = self._start_clock()
+
+        def retire(block: bool):
+            nonlocal done
+            while inflight and (block or len(inflight) > self.max_inflight or inflight[0][0].query()):
+                ev, fin = inflight.popleft()
+                ev.synchronize()
+                t = ref.elapsed_time(ev) * 1e-3
+                for j in fin:
+                    j.finish = t
+                    self._free(j)
+                    done += 1
+                block = False
+
+        while done < n:
+            now = time.perf_counter() - t0
+            while nxt < n and jobs[nxt].arrival <= now:
+                queue.append(jobs[nxt])
+                nxt += 1
+            while queue and len(active) < self.max_batch:
+                j = queue[0]
+                if not self._place(j):
+                    break
+                queue.popleft()
+                j.admitted = now
+                self._init(j)
+                active.append(j)
+                fresh.add(j.index)
+                changed = True
+            if changed:
+                self.batch.set([(j.cfg, j.U, j.ws) for j in active], fresh=[j.index in fresh for j in active],
+                               stream=self.stream)
+                fresh.clear()
+                changed = False
+            if active:
+                if self.use_graph:
+                    self.batch.step_graph(1, stream=self.stream)
+                else:
+                    self.batch.step(1, stream=self.stream)
+                steps += 1
+                max_seen = max(max_seen, len(active))
+                finished = []
+                for j in active:
+                    j.steps_done += 1
+                    if j.steps_done == j.steps:
+                        finished.append(j)
+                if finished:
+                    for j in finished:
+                        self._finish_job(j, keep_results)
+                    active = [j for j in active if j.steps_done < j.steps]
+                    changed = True
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.stream)
+                inflight.append((ev, finished))
+                retire(False)
+            elif inflight:
+                retire(True)
+            elif nxt < n:
+                time.sleep(max(0.0, jobs[nxt].arrival - (time.perf_counter() - t0)))
+            elif queue:
+                raise RuntimeError("a request does not fit in the arena")
+        retire(True)
+        self.batch.set([], stream=self.stream)
+        return self._stats("batched-graph" if self.use_graph else "batched", jobs, max_seen, steps)
+
+    def run_sequential(self, jobs: list[Job], keep_results: bool = False) -> RunStats:
+        """Serve the jobs one at a time (arrival order) with the single-problem advance call."""
+        jobs = sorted(jobs, key=lambda j: j.arrival)
+        inflight: deque = deque()
+        ref, t0 = self._start_clock()
+
+        def retire(block: bool):
+            while inflight and (block or len(inflight) > self.max_inflight or inflight[0][0].query()):
+                ev, j = inflight.popleft()
+                ev.synchronize()
+                j.finish = ref.elapsed_time(ev) * 1e-3
+                self._free(j)
+                block = False
+
+        for j in jobs:
+            while time.perf_counter() - t0 < j.arrival:
+                if inflight and inflight[0][0].query():
+                    retire(False)
+                else:
+                    time.sleep(min(1e-4, max(0.0, j.arrival - (time.perf_counter() - t0))))
+            while not self._place(j):
+                if not inflight:
+                    raise RuntimeError("a request does not fit in the arena")
+                retire(True)
+            j.admitted = time.perf_counter() - t0
+            self._init(j)
+            S.advance(j.cfg, j.U, j.steps, 0.0, j.ws, stream=self.stream)
+            j.steps_done = j.steps
+            self._finish_job(j, keep_results)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(self.stream)
+            inflight.append((ev, j))
+            retire(False)
+        retire(True)
+        while inflight:
+            retire(True)
+        return self._stats("sequential", jobs, 1, 0)
+
+    @staticmethod
+    def _stats(mode, jobs, max_seen, steps) -> RunStats:
+        lat = np.array([j.latency for j in jobs])
+        start = min(j.arrival for j in jobs)
+        end = max(j.finish for j in jobs)
+        return RunStats(mode=mode, n=len(jobs), makespan=end - start, latencies=lat,
+                        cell_updates=sum(j.cell_updates for j in jobs), max_batch_seen=max_seen,
+                        steps_launched=steps)
+
+    def close(self):
+        self.batch.close()

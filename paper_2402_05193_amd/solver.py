@@ -25,7 +25,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
 EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rk3_stage",
-            "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "check_state", "last_error"]
+            "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "adjoint_workspace_bytes",
+            "rk3_step_adjoint", "check_state", "workspace_time",
+            "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
+            "last_error"]
 
 
 class FVError(RuntimeError):
@@ -138,7 +141,17 @@ def lib():
         L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
         L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
         L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
+        L.adjoint_workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+        L.rk3_step_adjoint.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
         L.check_state.argtypes = [cp, vp, vp, ctypes.POINTER(Report), vp]
+        L.workspace_time.argtypes = [cp, vp, ctypes.POINTER(ctypes.c_double), vp]
+        L.batch_table_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.batch_create.argtypes = [ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.batch_destroy.argtypes = [vp]
+        L.batch_set.argtypes = [vp, ctypes.c_int32, cp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                ctypes.POINTER(ctypes.c_int32), vp]
+        L.batch_step.argtypes = [vp, ctypes.c_int32, vp]
+        L.batch_step_graph.argtypes = [vp, ctypes.c_int32, vp]
         L.last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("last_error",):
@@ -280,9 +293,29 @@ def advance(cfg: Config, U: torch.Tensor, nsteps: int, dt: float, ws: torch.Tens
     return tv.value if tv is not None else None
 
 
-def rhs_adjoint(cfg: Config, U, Rbar, Ubar, ws, stream=None):
+def rhs_adjoint(cfg: Config, U, Rbar, Ubar, ws=None, stream=None):
+    """Ubar = (dR/dU)^T Rbar at U (overwrites Ubar)."""
+    for t, n in ((U, "U"), (Rbar, "Rbar"), (Ubar, "Ubar")):
+        _state(cfg, t, n)
     c = cfg.c_struct()
     _check(lib().rhs_adjoint(ctypes.byref(c), _ptr(U), _ptr(Rbar), _ptr(Ubar), _ptr(ws), _stream(stream)))
+    return Ubar
+
+
+def adjoint_workspace(cfg: Config, device="cuda") -> torch.Tensor:
+    c = cfg.c_struct()
+    out = ctypes.c_size_t(0)
+    _check(lib().adjoint_workspace_bytes(ctypes.byref(c), ctypes.byref(out)))
+    return torch.empty(out.value, dtype=torch.uint8, device=device)
+
+
+def rk3_step_adjoint(cfg: Config, Un: torch.Tensor, Ubar: torch.Tensor, dt: float, aws: torch.Tensor, stream=None):
+    """In place: Ubar (cotangent of U^{n+1}) becomes the cotangent of U^n for one fixed-dt step from Un."""
+    _state(cfg, Un, "Un")
+    _state(cfg, Ubar, "Ubar")
+    c = cfg.c_struct()
+    _check(lib().rk3_step_adjoint(ctypes.byref(c), _ptr(Un), _ptr(Ubar), float(dt), _ptr(aws), _stream(stream)))
+    return Ubar
 
 
 def check_state(cfg: Config, U: torch.Tensor, ws: torch.Tensor, stream=None) -> Report:
@@ -304,3 +337,64 @@ def config_from_case(case, dtype: int = F64, **over) -> Config:
     kw = case.cfg_kwargs()
     kw.update(over)
     return Config(dtype=dtype, **kw)
+
+
+def workspace_time(cfg: Config, ws: torch.Tensor, stream=None) -> float:
+    """Simulated time held in a workspace (synchronises the stream)."""
+    c = cfg.c_struct()
+    t = ctypes.c_double(0.0)
+    _check(lib().workspace_time(ctypes.byref(c), _ptr(ws), ctypes.byref(t), _stream(stream)))
+    return t.value
+
+
+class Batch:
+    """Handle of a batch of independent problems stepped together (``batch_*`` of the C ABI).
+
+    The device request table is a tensor owned by this object; states and
+    workspaces belong to the caller and must stay alive while they are members.
+    """
+
+    def __init__(self, capacity: int, device="cuda"):
+        nb = ctypes.c_size_t(0)
+        _check(lib().batch_table_bytes(int(capacity), ctypes.byref(nb)))
+        self.capacity = int(capacity)
+        self.table = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p(0)
+        _check(lib().batch_create(self.capacity, _ptr(self.table), nb.value, ctypes.byref(h)))
+        self._h = h
+        self.members: list = []
+
+    def set(self, members, fresh=None, stream=None):
+        """members: sequence of (Config, U, ws); fresh: flags of members whose time stepping starts now."""
+        n = len(members)
+        cfgs = (_Cfg * max(1, n))()
+        Us = (ctypes.c_void_p * max(1, n))()
+        wss = (ctypes.c_void_p * max(1, n))()
+        fr = (ctypes.c_int32 * max(1, n))()
+        for i, (cfg, U, ws) in enumerate(members):
+            _state(cfg, U, f"U[{i}]")
+            if ws.numel() < workspace_bytes(cfg):
+                raise ValueError(f"ws[{i}]: smaller than workspace_bytes")
+            cfgs[i] = cfg.c_struct()
+            Us[i] = _ptr(U)
+            wss[i] = _ptr(ws)
+            fr[i] = 1 if (fresh is not None and fresh[i]) else 0
+        _check(lib().batch_set(self._h, n, cfgs, Us, wss, fr, _stream(stream)))
+        self.members = list(members)
+
+    def step(self, nsteps: int = 1, stream=None):
+        _check(lib().batch_step(self._h, int(nsteps), _stream(stream)))
+
+    def step_graph(self, nsteps: int = 1, stream=None):
+        _check(lib().batch_step_graph(self._h, int(nsteps), _stream(stream)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().batch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -353,3 +353,116 @@ def shock_bubble(nx: int = 256, ny: int = 128, nz: int = 128, ma: float = 1.22, 
         W[6] = a1
         case.W = W
     return case
+
+
+# --------------------------------------------------------------------------
+# Serving workload: a stream of independent three-dimensional Riemann problems
+# --------------------------------------------------------------------------
+SERVING_GRIDS = ((64, 64, 64), (96, 96, 96), (128, 128, 128), (192, 96, 96), (256, 128, 128))
+
+
+@dataclass
+class RiemannRequest:
+    """One request of the serving stream: a planar Riemann problem normal to x
+    at mid-domain in a box of cubic cells (h = 1/nx, domain [0,1] x [0,ny h] x
+    [0,nz h]), zero-gradient boundaries, tangential velocity 0.  Two-phase
+    requests carry fluid 1 (gamma 1.4) on the left and fluid 2 (gamma 1.66) on
+    the right with volume fractions 1 - ALPHA_EPS / ALPHA_EPS."""
+    index: int
+    model: int
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    WL: tuple
+    WR: tuple
+    left: tuple    # (rho, u, p, gamma) for an exact solution
+    right: tuple
+    gamma1: float
+    gamma2: float
+    steps: int
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def cfg_kwargs(self) -> dict:
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, dx=self.h, dy=self.h, dz=self.h, model=self.model,
+                    bc=(ZERO_GRADIENT,) * 6, gamma1=self.gamma1, gamma2=self.gamma2, positivity=1)
+
+    def riemann_params(self) -> list:
+        """Parameters of the planar two-state initial condition: axis, x0 fraction, W_L, W_R."""
+        return [0.0, 0.5, *self.WL, *self.WR]
+
+
+def riemann_request(index: int, seed: int = 2402, grids=SERVING_GRIDS, steps: int = 50,
+                    two_phase_fraction: float = 0.5) -> RiemannRequest:
+    """Request number ``index`` of the serving stream (seeded, reproducible).
+
+    rho in [0.1, 10], p in [0.1, 10], normal velocity in [-1, 1] on each side,
+    uniform draws.  Draws that would open a vacuum (u_R - u_L at or above
+    2 c_L/(gamma_L - 1) + 2 c_R/(gamma_R - 1)) are redrawn."""
+    attempt = 0
+    while True:
+        ctr = np.arange(16, dtype=np.uint64) + np.uint64(16 * (index * 64 + attempt))
+        u = uniform01(seed, ctr)
+        g = grids[min(int(u[0] * len(grids)), len(grids) - 1)]
+        model = DIM if u[1] < two_phase_fraction else EULER
+        u = [float(x) for x in u]
+        rl, rr = 0.1 + 9.9 * u[2], 0.1 + 9.9 * u[3]
+        pl, pr = 0.1 + 9.9 * u[4], 0.1 + 9.9 * u[5]
+        ul, ur = -1.0 + 2.0 * u[6], -1.0 + 2.0 * u[7]
+        gl, gr = (1.4, 1.66) if model == DIM else (1.4, 1.4)
+        cl, cr = math.sqrt(gl * pl / rl), math.sqrt(gr * pr / rr)
+        if 2 * cl / (gl - 1) + 2 * cr / (gr - 1) > (ur - ul):
+            break
+        attempt += 1
+    if model == DIM:
+        a, b = 1.0 - ALPHA_EPS, ALPHA_EPS
+        WL = (a * rl, (1 - a) * rl, ul, 0.0, 0.0, pl, a)
+        WR = (b * rr, (1 - b) * rr, ur, 0.0, 0.0, pr, b)
+    else:
+        WL = (rl, ul, 0.0, 0.0, pl)
+        WR = (rr, ur, 0.0, 0.0, pr)
+    nx, ny, nz = g
+    return RiemannRequest(index=index, model=model, nx=nx, ny=ny, nz=nz, h=1.0 / nx, WL=WL, WR=WR,
+                          left=(rl, ul, pl, gl), right=(rr, ur, pr, gr), gamma1=1.4,
+                          gamma2=1.66 if model == DIM else 1.4, steps=steps)
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 2402) -> np.ndarray:
+    """Arrival times (s) of the first n events of a Poisson process of the given rate."""
+    u = uniform01(seed ^ 0x5EED, np.arange(n, dtype=np.uint64))
+    return np.cumsum(-np.log1p(-u) / rate)
+
+
+# --------------------------------------------------------------------------
+# Differentiation workload: compressible decaying turbulence
+# --------------------------------------------------------------------------
+def decaying_turbulence(n: int, seed: int = 0, urms: float = 0.3, k0: float = 4.0, gamma: float = 1.4):
+    """Primitive state of compressible decaying turbulence on [0, 2pi)^3: rho = 1,
+    p = 1/gamma, solenoidal velocity with random phases and energy spectrum
+    E(k) ~ k^4 exp(-2 (k/k0)^2), scaled to u_rms = sqrt(<u.u>/3) = urms.
+    Seeded; built with an FFT on the host."""
+    k1 = np.fft.fftfreq(n, d=1.0 / n)
+    KZ, KY, KX = np.meshgrid(k1, k1, k1, indexing="ij")
+    K = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    ctr = np.arange(6 * n ** 3, dtype=np.uint64).reshape(6, n, n, n)
+    u = uniform01(seed, ctr)
+    # complex Gaussian amplitudes (Box-Muller), one per component
+    r = np.sqrt(-2.0 * np.log1p(-u[0:3]))
+    ph = 2.0 * math.pi * u[3:6]
+    A = r * np.exp(1j * ph)
+    # project out the component along k (divergence-free), shape by the spectrum
+    Kn = np.where(K > 0, K, 1.0)
+    kv = np.stack([KX, KY, KZ]) / Kn
+    A = A - kv * (kv * A).sum(0)
+    amp = np.where(K > 0, K ** 2 * np.exp(-((K / k0) ** 2)) / Kn, 0.0)   # |u_k| ~ sqrt(E(k)/k^2)
+    vel = np.real(np.fft.ifftn(A * amp, axes=(1, 2, 3)))
+    vel -= vel.mean(axis=(1, 2, 3), keepdims=True)
+    vel *= urms / math.sqrt((vel ** 2).sum(0).mean() / 3.0)
+    W = np.empty((5, n, n, n))
+    W[0] = 1.0
+    W[1], W[2], W[3] = vel[0], vel[1], vel[2]
+    W[4] = 1.0 / gamma
+    return W

@@ -75,7 +75,15 @@ def test_stage_and_step_validation():
     assert L.advance(ctypes.byref(c), 256, -1, 1e-3, None, 512, None) == S.EINVAL
     c2 = cfg(cfl=0.0).c_struct()
     assert L.advance(ctypes.byref(c2), 256, 3, 0.0, None, 512, None) == S.EINVAL
-    assert L.rhs_adjoint(ctypes.byref(c), 256, 512, 768, 1024, None) == S.EUNSUPPORTED
+    # the adjoint covers single-phase Euler, FP64, limiters off
+    for bad in (cfg(model=S.NS, mu=0.01), cfg(model=S.DIM), cfg(dtype=S.F32), cfg(positivity=1)):
+        cb = bad.c_struct()
+        assert L.rhs_adjoint(ctypes.byref(cb), 256, 512, 768, None, None) == S.EUNSUPPORTED
+        assert L.rk3_step_adjoint(ctypes.byref(cb), 256, 512, 1e-3, 768, None) == S.EUNSUPPORTED
+    assert L.rhs_adjoint(ctypes.byref(c), 256, 512, 256, None, None) == S.EINVAL    # Ubar aliases U
+    assert L.rhs_adjoint(ctypes.byref(c), 256, None, 768, None, None) == S.ENULL
+    assert L.rk3_step_adjoint(ctypes.byref(c), 256, 512, 0.0, 768, None) == S.EINVAL  # dt <= 0
+    assert L.rk3_step_adjoint(ctypes.byref(c), 256, 512, 1e-3, None, None) == S.ENULL
     assert L.init_state(ctypes.byref(c), 99, None, 0, 0, 256, None) == S.EINVAL
     p = (ctypes.c_double * 2)(0.1, 1.0)
     assert L.init_state(ctypes.byref(c), S.CASE_TGV, p, 2, 0, 256, None) == S.EINVAL  # too few params
@@ -89,3 +97,7 @@ def test_workspace_and_ncomp():
     assert S.ncomp(c) == 5
     assert S.ncomp(cfg(model=S.DIM)) == 7
     assert S.workspace_bytes(cfg(dtype=S.F32)) == 2 * ((4 * 5 * 512 + 255) // 256 * 256) + 256
+    out = ctypes.c_size_t(0)
+    cs = c.c_struct()
+    assert S.lib().adjoint_workspace_bytes(ctypes.byref(cs), ctypes.byref(out)) == S.OK
+    assert out.value == 5 * pad
