@@ -112,6 +112,66 @@ def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: 
     return out
 
 
+def run_adjoint_bench(n: int = 64, nsteps: int = 100, every: int = 10) -> dict:
+    """Differentiation workload: gradient of the kinetic energy after nsteps fixed-dt
+    TVD-RK3 steps of 64^3 decaying turbulence (Euler, FP64, WENO-Z eps 1e-6) with
+    respect to the initial state, through the hand-written adjoint with checkpoints."""
+    import math
+    import torch
+    from paper_2402_05193_amd import adjoint as AD
+    from paper_2402_05193_amd import solver as S
+    from paper_2402_05193_amd import workloads as WL
+
+    h = 2 * math.pi / n
+    cfg = S.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=S.EULER, dtype=S.F64, weno_eps=1e-6, cfl=0.5)
+    W = torch.from_numpy(WL.decaying_turbulence(n, seed=0)).cuda()
+    U = S.empty_state(cfg)
+    S.prim_to_cons(cfg, W, U)
+    ws = S.workspace(cfg)
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.compute_dt(cfg, U, dtd, ws)
+    dt = float(dtd)
+    Rbar = torch.randn(U.shape, dtype=torch.float64, device="cuda")
+    Ubar = torch.empty_like(U)
+    for _ in range(3):
+        S.rhs_adjoint(cfg, U, Rbar, Ubar)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        S.rhs_adjoint(cfg, U, Rbar, Ubar)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / reps
+    R = torch.empty_like(U)
+    e0.record()
+    for _ in range(reps):
+        S.rhs(cfg, U, R)
+    e1.record()
+    torch.cuda.synchronize()
+    rhs_ms = e0.elapsed_time(e1) / reps
+    # forward alone, then forward + backward of the whole trajectory
+    X = U.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.advance(cfg, X, nsteps, dt, ws)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t0
+    U0 = U.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = AD.kinetic_energy(cfg, AD.advance_fixed_dt(cfg, U0, nsteps, dt, every=every))
+    (g,) = torch.autograd.grad(L, U0)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    return {"workload": f"gradient of kinetic energy after {nsteps} fixed-dt TVD-RK3 steps, {n}^3 decaying "
+                        f"turbulence (Euler, FP64, WENO-Z eps 1e-6), checkpoints every {every} steps",
+            "rhs_adjoint_ms": adj_ms, "rhs_ms": rhs_ms, "adjoint_over_rhs": adj_ms / rhs_ms,
+            "forward_s": fwd_s, "forward_plus_gradient_s": grad_s, "gradient_over_forward": grad_s / fwd_s,
+            "loss": float(L), "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +188,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-batch", type=int, default=32)
     ap.add_argument("--serve-pool-gib", type=float, default=12.0)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -253,6 +314,9 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_max_batch,
                                      args.serve_pool_gib)
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint_bench()
+        print(f"[bench] adjoint: {json.dumps(out['adjoint'])}", flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_oracle_baseline(args.n, model)
     print(json.dumps(out), flush=True)

@@ -170,7 +170,12 @@ int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_
  * |x|' = sgn(x) with sgn(0) = 0, an even split at ties of min/max, and a zero
  * derivative of the HLLC upwind switch.  Contributions are accumulated with
  * atomic adds: reproducible to round-off, not bitwise.  ws is unused (may be
- * NULL).  Ubar must not overlap U or Rbar. */
+ * NULL).  Ubar must not overlap U or Rbar.
+ * Conditioning: at a constant reconstruction stencil (uniform regions,
+ * zero-gradient halos) the smoothness indicators are round-off and the
+ * derivative of the WENO-Z weights scales like 1/(beta + weno_eps)^2; with the
+ * default epsilon 1e-40 it is then set by rounding.  Reproducible gradients of
+ * such fields need a larger epsilon (e.g. 1e-6, the same in the forward). */
 int rhs_adjoint(const fv_config* cfg, const void* U, const void* Rbar, void* Ubar, void* ws,
                 void* stream);
 
