@@ -17,9 +17,11 @@ view (algorithmic bytes over the same duration) is reported beside it.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -45,6 +47,37 @@ def flops_per_cell(model: int) -> int:
     div = 9 * nc + (7 if model == 2 else 0)
     rk = 5 * nc
     return weno + hllc + visc + conv + div + rk
+
+
+PROFILE_MD = os.path.join(ROOT, "profiles", "stage_kernel_ns_tgv256_f64.md")
+KERNEL_SOURCES = ("fv_stage.hip", "fv_physics.h", "fv_kernels.h")
+
+
+def stage_kernel_hash() -> str:
+    """Fingerprint of the stage kernel: its sources and the compiler flags."""
+    from paper_2402_05193_amd import build as B
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(B.CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(B.FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per stage-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel of known size) recorded in the committed rocprofv3 summary, if it was
+    taken on the current kernel (same fingerprint) and workload; else None."""
+    if not os.path.exists(PROFILE_MD):
+        return None
+    want = stage_kernel_hash()
+    pat = re.compile(r"traffic-record: kernel=(\w+) workload=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)")
+    with open(PROFILE_MD) as fh:
+        for line in fh:
+            m = pat.search(line)
+            if m and m.group(1) == want and m.group(2) == workload_key:
+                return int(m.group(3)) + int(m.group(4))
+    return None
 
 
 def bytes_per_cell(nc: int, es: int, stage: int) -> int:
@@ -283,6 +316,8 @@ def main():
     hbm_gbs = alg_bytes / (mean_stage_ms * 1e-3) / 1e9
 
     finite = bool(torch.isfinite(U).all().item())
+    workload_key = f"{args.model}-{args.dtype}-{args.n}"
+    traffic = measured_traffic(workload_key)
     out = {
         "metric": "cell-updates/s + % HBM roofline (RK3 stage, 256^3); batched p50/p99 latency",
         "value": value,
@@ -302,8 +337,8 @@ def main():
         "stage_ms": {"mean": mean_stage_ms, "stage1": sum(stage_ms[0]) / args.steps,
                      "stage2": sum(stage_ms[1]) / args.steps, "stage3": sum(stage_ms[2]) / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / peak, "traffic": None,
-                     "kernel": "stage_kernel", "flops_per_cell": fpc},
+                     "frac": achieved_tflops / peak, "traffic": traffic,
+                     "kernel": "stage_kernel", "flops_per_cell": fpc, "kernel_fingerprint": stage_kernel_hash()},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell},
         "wall_s": wall,

@@ -37,7 +37,7 @@
 #define FV_RECON_ITEMS 1
 #endif
 #ifndef FV_KERNARG_INPLACE
-#define FV_KERNARG_INPLACE 0
+#define FV_KERNARG_INPLACE 1
 #endif
 #ifndef FV_RECON_UNROLL
 #define FV_RECON_UNROLL 1

@@ -47,27 +47,25 @@ struct Tolerances {
 };
 
 // ---------------------------------------------------------------- arithmetic helpers
-// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
-// (FP64: good to about an ulp for the positive normal arguments used here;
-// FP32: the single-precision estimates are used as they are).
+// 1/x and 1/sqrt(x) from the hardware estimates (relative error below 2^-24
+// on gfx950, measured) with one third-order correction: for r = 1/x (1 - e),
+// 1/x = r (1 + e + e^2 + O(e^3)); for y = (1 - e)^(1/2) / sqrt(x) with
+// e = 1 - x y^2, 1/sqrt(x) = y (1 + e/2 + 3 e^2/8 + O(e^3)).  The O(e^3) terms
+// are below 2^-70, so the FP64 results are good to about an ulp for the
+// positive normal arguments used here.  FP32 uses the estimates as they are.
 __device__ __forceinline__ double rcp(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ double rsqrt(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-h * y, y, 0.5);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
 }
 __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
