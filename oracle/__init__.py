@@ -37,7 +37,7 @@ class _Cfg(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("model", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 6),
-        ("positivity", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("positivity", ctypes.c_int32), ("recon", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
         ("gamma1", ctypes.c_double), ("pinf1", ctypes.c_double),
         ("gamma2", ctypes.c_double), ("pinf2", ctypes.c_double),
@@ -69,6 +69,7 @@ class Config:
     eps_rhoc2: float = 1e-10
     eps_alpha: float = 1e-12
     weno_eps: float = 1e-40
+    recon: int = 0                # 0: primitive variables, 1: characteristic variables
 
     @property
     def ncomp(self) -> int:
@@ -93,6 +94,7 @@ class Config:
         c.mu, c.prandtl = self.mu, self.prandtl
         c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
         c.weno_eps = self.weno_eps
+        c.recon = self.recon
         return c
 
 
@@ -117,6 +119,7 @@ def lib():
         L.orc_dt.restype = ctypes.c_double
         L.orc_advance.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.orc_advance.restype = ctypes.c_double
+        L.orc_char_matrices.argtypes = [cp, ctypes.c_int, dp, dp, dp]
         L.orc_face_count.argtypes = [cp, ctypes.c_int]
         L.orc_face_count.restype = ctypes.c_long
         L.orc_max_threads.restype = ctypes.c_int
@@ -234,6 +237,17 @@ def advance(cfg: Config, U, nsteps: int, dt: float = 0.0, cfl: float = 0.5):
     c = cfg.c_struct()
     t = lib().orc_advance(ctypes.byref(c), _dp(U), int(nsteps), float(dt), float(cfl))
     return U, t
+
+
+def char_matrices(cfg: Config, d: int, W):
+    """Right eigenvectors K (columns) of A(W) for direction d and K^{-1} (Sec. 3.2, appendix)."""
+    nc = cfg.ncomp
+    W = _arr(W, (nc,))
+    K = np.zeros((nc, nc))
+    Ki = np.zeros((nc, nc))
+    c = cfg.c_struct()
+    lib().orc_char_matrices(ctypes.byref(c), int(d), _dp(W), _dp(K), _dp(Ki))
+    return K, Ki
 
 
 def max_threads() -> int:

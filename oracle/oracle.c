@@ -55,7 +55,7 @@ typedef struct {
     int32_t model;
     int32_t bc[6];       /* x-, x+, y-, y+, z-, z+ */
     int32_t positivity;  /* 1: interpolation + flux limiter (Sec. 3.3) */
-    int32_t pad_;
+    int32_t recon;       /* 0: primitive variables, 1: characteristic variables (Sec. 3.2) */
     double dx, dy, dz;
     double gamma1, pinf1, gamma2, pinf2;
     double mu, prandtl;
@@ -512,20 +512,135 @@ static int active_dims(const orc_cfg *c)
     return (c->nx > 1) + (c->ny > 1) + (c->nz > 1);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Characteristic decomposition (Sec. 3.2 steps 1, 2 and 4; appendix        */
+/* "Characteristic decomposition").  K: right eigenvectors of A(W) for the  */
+/* face normal d, as printed in the appendix with the rows of the normal    */
+/* and tangential velocities permuted for d; columns: acoustic (u - c),     */
+/* the advected fields, acoustic (u + c).  K^{-1} is obtained by Gauss-     */
+/* Jordan elimination of K.                                                  */
+/* ------------------------------------------------------------------------ */
+static void char_right(const orc_cfg *c, int d, const double *W, double K[MAXC][MAXC])
+{
+    int nc = orc_ncomp(c), v = vel0(c), P = pidx(c);
+    double rho = w_density(c, W);
+    double rc2 = w_rhoc2(c, W);
+    double cs = sqrt(rc2 / rho);
+    int t1 = v + (d + 1) % 3, t2 = v + (d + 2) % 3, un = v + d;
+    for (int r = 0; r < nc; r++)
+        for (int q = 0; q < nc; q++) K[r][q] = 0.0;
+    int last = nc - 1;
+    /* acoustic columns: densities (phase densities for DIM), -/+ c on u_n, rho c^2 on p */
+    if (c->model == M_DIM) {
+        K[0][0] = W[0]; K[1][0] = W[1];
+        K[0][last] = W[0]; K[1][last] = W[1];
+    } else {
+        K[0][0] = rho; K[0][last] = rho;
+    }
+    K[un][0] = -cs; K[un][last] = cs;
+    K[P][0] = rc2; K[P][last] = rc2;
+    /* advected fields: densities, the two tangential velocities, the volume fraction */
+    if (c->model == M_DIM) {
+        K[0][1] = 1.0;
+        K[1][2] = 1.0;
+        K[t1][3] = 1.0;
+        K[t2][4] = 1.0;
+        K[6][5] = 1.0;
+    } else {
+        K[0][1] = 1.0;
+        K[t1][2] = 1.0;
+        K[t2][3] = 1.0;
+    }
+}
+
+/* inverse of an n x n matrix by Gauss-Jordan elimination with partial pivoting */
+static void invert(int n, double A[MAXC][MAXC], double Inv[MAXC][MAXC])
+{
+    double M[MAXC][2 * MAXC];
+    for (int r = 0; r < n; r++)
+        for (int q = 0; q < 2 * n; q++) M[r][q] = q < n ? A[r][q] : (q - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; col++) {
+        int piv = col;
+        for (int r = col + 1; r < n; r++)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (piv != col)
+            for (int q = 0; q < 2 * n; q++) { double t = M[col][q]; M[col][q] = M[piv][q]; M[piv][q] = t; }
+        double inv = 1.0 / M[col][col];
+        for (int q = 0; q < 2 * n; q++) M[col][q] *= inv;
+        for (int r = 0; r < n; r++) {
+            if (r == col || M[r][col] == 0.0) continue;
+            double f = M[r][col];
+            for (int q = 0; q < 2 * n; q++) M[r][q] -= f * M[col][q];
+        }
+    }
+    for (int r = 0; r < n; r++)
+        for (int q = 0; q < n; q++) Inv[r][q] = M[r][q + n];
+}
+
+/* Face states W^-/+ at the face between cells i and i+1 (direction d) from the
+ * six-cell stencil v[s] = W_{i-2+s}: WENO5-Z of each primitive component
+ * (recon 0), or of each characteristic component of the frozen face state
+ * W_{i+1/2} = (W_i + W_{i+1})/2 (recon 1). */
+static void reconstruct(const orc_cfg *c, int d, double v[6][MAXC], double *WL, double *WR)
+{
+    int nc = orc_ncomp(c);
+    if (c->recon != 1) {
+        for (int m = 0; m < nc; m++) {
+            WL[m] = orc_weno5z(v[0][m], v[1][m], v[2][m], v[3][m], v[4][m], c->weno_eps);
+            WR[m] = orc_weno5z(v[5][m], v[4][m], v[3][m], v[2][m], v[1][m], c->weno_eps);
+        }
+        return;
+    }
+    double Wf[MAXC], K[MAXC][MAXC], Kinv[MAXC][MAXC], ch[6][MAXC], cl[MAXC], cr[MAXC];
+    for (int m = 0; m < nc; m++) Wf[m] = 0.5 * (v[2][m] + v[3][m]);
+    char_right(c, d, Wf, K);
+    invert(nc, K, Kinv);
+    for (int s = 0; s < 6; s++)
+        for (int q = 0; q < nc; q++) {
+            double acc = 0.0;
+            for (int m = 0; m < nc; m++) acc += Kinv[q][m] * v[s][m];
+            ch[s][q] = acc;
+        }
+    for (int q = 0; q < nc; q++) {
+        cl[q] = orc_weno5z(ch[0][q], ch[1][q], ch[2][q], ch[3][q], ch[4][q], c->weno_eps);
+        cr[q] = orc_weno5z(ch[5][q], ch[4][q], ch[3][q], ch[2][q], ch[1][q], c->weno_eps);
+    }
+    for (int m = 0; m < nc; m++) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < nc; q++) {
+            a += K[m][q] * cl[q];
+            b += K[m][q] * cr[q];
+        }
+        WL[m] = a;
+        WR[m] = b;
+    }
+}
+
+/* K and K^{-1} at a primitive state (exported for the tests) */
+void orc_char_matrices(const orc_cfg *c, int d, const double *W, double *K, double *Kinv)
+{
+    int nc = orc_ncomp(c);
+    double A[MAXC][MAXC], B[MAXC][MAXC];
+    char_right(c, d, W, A);
+    invert(nc, A, B);
+    for (int r = 0; r < nc; r++)
+        for (int q = 0; q < nc; q++) {
+            K[r * nc + q] = A[r][q];
+            Kinv[r * nc + q] = B[r][q];
+        }
+}
+
 static void face_flux(const orc_cfg *c, const padded *p, int d, int i, int j, int k, double dt,
                       double *F, double *uh, int *flags)
 {
     int nc = orc_ncomp(c);
     const int *o = DI[d];
     double WL[MAXC], WR[MAXC];
-    /* step 3: WENO5-Z of every primitive component, both sides */
-    for (int m = 0; m < nc; m++) {
-        double v[6];
-        for (int s = 0; s < 6; s++)
-            v[s] = get_q(p, m, i + (s - 2) * o[0], j + (s - 2) * o[1], k + (s - 2) * o[2]);
-        WL[m] = orc_weno5z(v[0], v[1], v[2], v[3], v[4], c->weno_eps);
-        WR[m] = orc_weno5z(v[5], v[4], v[3], v[2], v[1], c->weno_eps);
-    }
+    /* step 3: WENO5-Z reconstruction, both sides */
+    double v[6][MAXC];
+    for (int s = 0; s < 6; s++)
+        get_w(p, i + (s - 2) * o[0], j + (s - 2) * o[1], k + (s - 2) * o[2], v[s]);
+    reconstruct(c, d, v, WL, WR);
     double Wi[MAXC], Wip[MAXC];
     get_w(p, i, j, k, Wi);
     get_w(p, i + o[0], j + o[1], k + o[2], Wip);

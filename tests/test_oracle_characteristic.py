@@ -1,0 +1,156 @@
+"""Pins of the oracle's characteristic-variable reconstruction (Sec. 3.2 steps
+1-4, appendix "Characteristic decomposition"), CPU only.
+
+* The columns of K are eigenvectors of the quasi-linear flux Jacobian
+  A = (dU/dW)^{-1} dF/dW, which is built here by central differences of the
+  oracle's own conservative map and physical flux (the HLLC flux of two equal
+  states), with eigenvalues u_n - c, u_n (multiple), u_n + c.
+* Where only an advected field varies (the paper's Gaussian density wave), the
+  projection is exact and the result equals the primitive reconstruction.
+* A uniform state gives R = 0 exactly; periodic domains conserve.
+* Characteristic and primitive reconstruction converge to the same limit:
+  their difference falls at least with the fourth power of the cell size.
+* Shock tubes against the exact Riemann solution, as for the primitive
+  reconstruction.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_05193_amd import workloads as WL
+from test_oracle_accuracy import tube_l1
+
+
+def flux_jacobian(cfg, d, W, h=1e-6):
+    """A = (dU/dW)^{-1} dF/dW by central differences of the oracle's conservative
+    map and physical flux."""
+    nc = cfg.ncomp
+    c1 = O.Config(nx=1, ny=1, nz=1, model=cfg.model, gamma1=cfg.gamma1, pinf1=cfg.pinf1, gamma2=cfg.gamma2,
+                  pinf2=cfg.pinf2)
+
+    def U_of(w):
+        return O.prim_to_cons(c1, np.asarray(w, dtype=float).reshape(nc, 1, 1, 1)).ravel()
+
+    def F_of(w):
+        F, _ = O.hllc(c1, d, w, w)
+        return np.asarray(F)
+
+    dU = np.zeros((nc, nc))
+    dF = np.zeros((nc, nc))
+    for q in range(nc):
+        e = np.zeros(nc)
+        e[q] = h * max(1.0, abs(W[q]))
+        dU[:, q] = (U_of(W + e) - U_of(W - e)) / (2 * e[q])
+        dF[:, q] = (F_of(W + e) - F_of(W - e)) / (2 * e[q])
+    if cfg.model == O.DIM:
+        # the volume-fraction equation carries the source alpha1 div(u) (Sec. 3.6): its
+        # quasi-linear coefficient is u_n on alpha1 only, not d(alpha1 u_n)/dW
+        dF[6, 2 + d] -= W[6]
+    return np.linalg.solve(dU, dF)
+
+
+STATES = [
+    (O.Config(4, 4, 4), np.array([1.3, 0.4, -0.2, 0.7, 2.1])),
+    (O.Config(4, 4, 4, gamma1=4.4, pinf1=6.0), np.array([1.1, -0.3, 0.5, 0.1, 0.8])),
+    (O.Config(4, 4, 4, model=O.DIM, gamma2=1.66), np.array([0.5, 0.3, 0.2, -0.4, 0.6, 1.7, 0.35])),
+    (O.Config(4, 4, 4, model=O.DIM, gamma1=6.12, pinf1=3.43, gamma2=1.4),
+     np.array([0.9, 0.05, -0.1, 0.2, 0.3, 2.5, 0.8])),
+]
+
+
+@pytest.mark.parametrize("idx", range(len(STATES)))
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_right_eigenvectors_of_the_flux_jacobian(idx, d):
+    cfg, W = STATES[idx]
+    nc = cfg.ncomp
+    K, Ki = O.char_matrices(cfg, d, W)
+    assert np.abs(K @ Ki - np.eye(nc)).max() < 1e-13
+    A = flux_jacobian(cfg, d, W)
+    un = W[(2 if nc == 7 else 1) + d]
+    lam = K[:, 0] * 0.0
+    AK = A @ K
+    # eigenvalue of each column from its largest entry
+    for q in range(nc):
+        r = np.argmax(np.abs(K[:, q]))
+        lam_q = AK[r, q] / K[r, q]
+        assert np.abs(AK[:, q] - lam_q * K[:, q]).max() <= 1e-6 * max(1.0, np.abs(AK).max())
+        lam = lam_q if q == 0 else lam
+        if q == 0:
+            c = un - lam_q
+        elif q == nc - 1:
+            assert abs(lam_q - (un + c)) <= 1e-6 * max(1.0, abs(un) + c)
+        else:
+            assert abs(lam_q - un) <= 1e-6 * max(1.0, abs(un) + c)
+    assert c > 0
+
+
+def rhs_pair(case, **kw):
+    cp = O.Config(**case.cfg_kwargs(), **kw)
+    cc = O.Config(**case.cfg_kwargs(), **kw, recon=1)
+    U = O.prim_to_cons(cp, case.W)
+    return O.rhs(cp, U), O.rhs(cc, U), U, cc
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_advected_field_equals_primitive_reconstruction(axis):
+    case = WL.gauss_wave(48, axis=axis)
+    Rp, Rc, _, _ = rhs_pair(case)
+    assert np.abs(Rc - Rp).max() <= 1e-12 * np.abs(Rp).max()
+
+
+def test_uniform_state_gives_zero_exactly():
+    for model, state in ((O.EULER, (1.0, 0.1, -0.2, 0.3, 1.0)),
+                         (O.DIM, (0.3, 0.5, 0.2, -0.1, 0.4, 1.3, 0.4))):
+        case = WL.uniform(9, 8, 7, model=model, state=state, gamma2=1.66)
+        _, Rc, _, _ = rhs_pair(case)
+        assert np.all(Rc == 0.0)
+
+
+def test_periodic_conservation():
+    case = WL.smooth_random(12, 10, 9, model=O.EULER, seed=4)
+    _, Rc, _, _ = rhs_pair(case)
+    for m in range(5):
+        assert abs(Rc[m].sum()) <= 1e-13 * np.abs(Rc[m]).sum()
+
+
+def test_two_phase_pressure_velocity_equilibrium():
+    """Uniform u and p across a volume-fraction / density jump stay uniform
+    (no spurious pressure oscillation from the projection)."""
+    n = 24
+    WLs = (0.8 * 1.2, 0.2 * 1.2, 0.3, 0.0, 0.0, 1.0, 0.8)
+    WRs = (0.1 * 0.4, 0.9 * 0.4, 0.3, 0.0, 0.0, 1.0, 0.1)
+    case = WL.riemann_planar(n, 1, 1, 0, 0.5, WLs, WRs, O.DIM, 1.0 / n, bc=(WL.PERIODIC,) * 6, gamma1=1.4,
+                             gamma2=1.66)
+    cc = O.Config(**case.cfg_kwargs(), recon=1)
+    U = O.prim_to_cons(cc, case.W)
+    dt = 0.2 * O.compute_dt(cc, U, 1.0)
+    W1 = O.cons_to_prim(cc, O.rk3_step(cc, U, dt))
+    assert np.abs(W1[2] - 0.3).max() <= 1e-12
+    assert np.abs(W1[5] - 1.0).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_characteristic_and_primitive_converge_together(seed):
+    """Both reconstructions approximate the same flux divergence to high order,
+    so their difference vanishes fast under refinement; the nonlinear weights
+    make single refinements noisy, so two are taken at once (64 -> 256 cells):
+    at least fourth order (a factor 256)."""
+    diffs = []
+    for n in (64, 256):
+        case = WL.smooth_random(n, 1, 1, model=O.EULER, seed=seed, amplitude=0.2)
+        Rp, Rc, _, _ = rhs_pair(case)
+        diffs.append(np.abs(Rc - Rp).max())
+    assert diffs[0] / diffs[1] > 256.0
+
+
+@pytest.mark.parametrize("name,limits", [
+    ("sod", (0.0024, 0.0052, 0.0018)),
+    ("air_helium", (0.0028, 0.0060, 0.0020)),
+])
+def test_shock_tube_with_characteristic_reconstruction(name, limits):
+    case = {"sod": WL.sod_tube, "air_helium": WL.air_helium_tube}[name](200)
+    case.cfg_kwargs_orig = case.cfg_kwargs
+    case.cfg_kwargs = lambda: {**case.cfg_kwargs_orig(), "recon": 1}
+    errs = tube_l1(case)
+    for e, lim in zip(errs, limits):
+        assert e < lim, (name, errs)
