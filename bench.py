@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--model", choices=["ns", "euler", "dim"], default="ns")
+    ap.add_argument("--recon", type=int, choices=[0, 1], default=0,
+                    help="reconstruction variables: 0 primitive (the benchmark), 1 characteristic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of known size first (for HBM counter scaling)")
@@ -239,7 +241,7 @@ def main():
     if model == S.DIM:
         case = WL.shock_bubble(2 * args.n if args.n < 256 else 256, args.n // 2 if args.n < 256 else 128,
                                args.n // 2 if args.n < 256 else 128, with_field=False)
-        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon)
         rho2, u2, p2 = case.meta["post_shock"]
         H = case.meta["H"]
         params = [0.060, 0.090, H / 2, H / 2, 0.25 * H, WL.ALPHA_EPS, rho2, u2, p2, 1.2041, 101325.0, 0.1660]
@@ -247,11 +249,12 @@ def main():
         workload = f"DIM shock-bubble Ma 1.22 air/He {cfg.nx}x{cfg.ny}x{cfg.nz}, limiters on, CFL 0.5"
     else:
         case = WL.taylor_green(args.n, viscous=(model == S.NS), with_field=False)
-        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon)
         params = [0.1, 1.0, 1e-3]
         case_id = S.CASE_TGV
         workload = (f"{'NS' if model == S.NS else 'Euler'} Taylor-Green vortex Ma 0.1"
-                    f"{' Re 1600 Pr 0.72' if model == S.NS else ''} periodic {args.n}^3, CFL 0.5")
+                    f"{' Re 1600 Pr 0.72' if model == S.NS else ''} periodic {args.n}^3, CFL 0.5"
+                    f"{', characteristic reconstruction' if args.recon else ''}")
 
     if args.copy_calibration:
         nbytes = 1 << 30
@@ -316,7 +319,7 @@ def main():
     hbm_gbs = alg_bytes / (mean_stage_ms * 1e-3) / 1e9
 
     finite = bool(torch.isfinite(U).all().item())
-    workload_key = f"{args.model}-{args.dtype}-{args.n}"
+    workload_key = f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
     traffic = measured_traffic(workload_key)
     out = {
         "metric": "cell-updates/s + % HBM roofline (RK3 stage, 256^3); batched p50/p99 latency",

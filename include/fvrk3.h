@@ -86,7 +86,10 @@ typedef struct fv_config {
     int32_t dtype;       /* fv_dtype of every array                        */
     int32_t bc[6];       /* fv_bc for x-, x+, y-, y+, z-, z+               */
     int32_t positivity;  /* 1: limiters on, 0: off, -1: default (on for DIM) */
-    int32_t reserved;    /* must be 0                                      */
+    int32_t recon;       /* reconstruction variables: 0 primitive (Sec. 3.2 as read
+                            here), 1 characteristic (Sec. 3.2 steps 1-4, frozen face
+                            state = mean of the two cells, appendix eigenvectors);
+                            batches and the adjoint take 0 only                 */
     double dx, dy, dz;   /* uniform cell sizes, > 0                        */
     double gamma1, pinf1;/* stiffened gas of fluid 1 (the only fluid for EULER/NS) */
     double gamma2, pinf2;/* stiffened gas of fluid 2 (FV_DIM)              */

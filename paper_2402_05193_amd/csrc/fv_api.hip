@@ -48,7 +48,7 @@ int validate(const fv_config* c)
     if ((long long)c->nx * c->ny * c->nz > (1ll << 40)) return fail(FV_EINVAL, "grid too large");
     if (c->model < FV_EULER || c->model > FV_DIM) return fail(FV_EINVAL, "model %d unknown", c->model);
     if (c->dtype != FV_F64 && c->dtype != FV_F32) return fail(FV_EINVAL, "dtype %d unknown", c->dtype);
-    if (c->reserved != 0) return fail(FV_EINVAL, "reserved must be 0");
+    if (c->recon != 0 && c->recon != 1) return fail(FV_EINVAL, "recon must be 0 or 1");
     const int n3[3] = {c->nx, c->ny, c->nz};
     for (int a = 0; a < 3; a++) {
         for (int s = 0; s < 2; s++) {
@@ -138,6 +138,7 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.nchunks = (c->nz + zc - 1) / zc;
     g.nblocks = (int)(tiles * a.nchunks);
     a.positivity = positivity_on(c) ? 1 : 0;
+    a.recon = c->recon;
     a.ndim = (c->nx > 1) + (c->ny > 1) + (c->nz > 1);
     a.mat = material<Real>(c);
     a.tol.eps_rho = (Real)(c->eps_rho > 0 ? c->eps_rho : (f64 ? 1e-12 : 1e-10));
@@ -411,6 +412,7 @@ static int adjoint_supported(const fv_config* cfg)
     if (cfg->model != FV_EULER) return fail(FV_EUNSUPPORTED, "the adjoint covers the single-phase Euler model");
     if (cfg->dtype != FV_F64) return fail(FV_EUNSUPPORTED, "the adjoint is FP64");
     if (positivity_on(cfg)) return fail(FV_EUNSUPPORTED, "the adjoint needs the positivity limiters off");
+    if (cfg->recon != 0) return fail(FV_EUNSUPPORTED, "the adjoint covers primitive-variable reconstruction");
     return FV_OK;
 }
 
@@ -680,6 +682,7 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if (r) return fail(r, "member %d: %s", i, last_error());
         if ((r = check_ptr(U[i], "U")) || (r = check_ptr(ws[i], "ws"))) return fail(r, "member %d: %s", i, last_error());
         if (!(cfgs[i].cfl > 0)) return fail(FV_EINVAL, "member %d: cfl must be > 0", i);
+        if (cfgs[i].recon != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use primitive reconstruction", i);
     }
     // groups in order of first appearance; members keep their order inside a group
     std::vector<BatchGroup> groups;

@@ -59,6 +59,7 @@ struct StageArgs {
     int bc[6];
     int tiles_x, tiles_y, zchunk, nchunks;
     int positivity, ndim;
+    int recon;           // 0: primitive variables, 1: characteristic variables
     Material<Real> mat;
     Tolerances<Real> tol;
     Real weno_eps;

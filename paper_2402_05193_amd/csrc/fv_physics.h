@@ -247,6 +247,97 @@ __device__ __forceinline__ void weno5z_pair(Real a, Real b, Real c, Real d, Real
     vp = (g2 * u0 + m1 * u1 + n2 * u2) * idp;
 }
 
+// One-sided WENO5-Z value v^-_{i+1/2} from v_{i-2..i+2} = a,b,c,d,e (the v^+
+// value of a face is the same function of the mirrored stencil).
+template <typename Real>
+__device__ __forceinline__ Real weno5z_one(Real a, Real b, Real c, Real d, Real e, Real eps)
+{
+    const Real k13 = Real(13.0 / 12.0), q = Real(0.25);
+    const Real t0 = a - Real(2) * b + c;
+    const Real s0 = a - Real(4) * b + Real(3) * c;
+    const Real t1 = b - Real(2) * c + d;
+    const Real s1 = b - d;
+    const Real t2 = c - Real(2) * d + e;
+    const Real s2 = Real(3) * c - Real(4) * d + e;
+    const Real b0 = k13 * t0 * t0 + q * s0 * s0;
+    const Real b1 = k13 * t1 * t1 + q * s1 * s1;
+    const Real b2 = k13 * t2 * t2 + q * s2 * s2;
+    const Real tau = fabs(b0 - b2);
+    const Real e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    Real r0, r1, r2;
+    if constexpr (sizeof(Real) == 8) {
+        const Real p01 = e0 * e1;
+        const Real R = rcp(p01 * e2);
+        const Real t = e2 * R;
+        r2 = p01 * R;
+        r0 = e1 * t;
+        r1 = e0 * t;
+    } else {
+        r0 = rcp(e0);
+        r1 = rcp(e1);
+        r2 = rcp(e2);
+    }
+    const Real g0 = fma(tau, r0, Real(1));
+    const Real m1 = Real(6) * fma(tau, r1, Real(1));
+    const Real m2 = Real(3) * fma(tau, r2, Real(1));
+    const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
+    const Real p1 = -b + Real(5) * c + Real(2) * d;
+    const Real p2 = Real(2) * c + Real(5) * d - e;
+    return (g0 * p0 + m1 * p1 + m2 * p2) * rcp(Real(6) * (g0 + m1 + m2));
+}
+
+// Face states by WENO5-Z of characteristic variables (Sec. 3.2 steps 1-4 and
+// the appendix eigenvectors).  st(s, m): component m of W at stencil slot s,
+// slots 0..5 = cells f-3 .. f+2 around the face between cells f-1 and f.  The
+// frozen face state is the mean of cells f-1 and f.  With rho c the acoustic
+// impedance and rho c^2 taken there, the projection K^{-1} W, scaled per
+// field, gives the acoustic variables p -/+ (rho c) u_n, the densities minus
+// their acoustic part (rho_k - (rho_k / (rho c^2)) p), and the tangential
+// velocities and the volume fraction unchanged; each is reconstructed from both
+// sides and mapped back with K.
+template <typename Real, int MODEL, int DIR, typename Stencil>
+__device__ __forceinline__ void char_face_states(const Material<Real>& mat, Stencil st, Real eps, Real* wl, Real* wr)
+{
+    constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V, P = Layout<MODEL>::P;
+    constexpr int UN = V + DIR, T1 = V + (DIR + 1) % 3, T2 = V + (DIR + 2) % 3;
+    constexpr int ND = MODEL == DIM ? 2 : 1;  // density fields
+    Real wf[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) wf[m] = Real(0.5) * (st(2, m) + st(3, m));
+    const Real rc2 = rhoc2<Real, MODEL>(mat, wf);
+    const Real irc2 = rcp(rc2);
+    const Real z = sqrt_fast(density<Real, MODEL>(wf) * rc2);  // rho c
+    const Real iz2 = Real(0.5) * rcp(z);
+    Real g[ND];
+#pragma unroll
+    for (int k = 0; k < ND; k++) g[k] = wf[k] * irc2;
+    auto both = [&](auto field, Real& L, Real& R) {
+        Real q[6];
+#pragma unroll
+        for (int s = 0; s < 6; s++) q[s] = field(s);
+        L = weno5z_one(q[0], q[1], q[2], q[3], q[4], eps);
+        R = weno5z_one(q[5], q[4], q[3], q[2], q[1], eps);
+    };
+    Real amL, amR, apL, apR;
+    both([&](int s) { return st(s, P) - z * st(s, UN); }, amL, amR);
+    both([&](int s) { return st(s, P) + z * st(s, UN); }, apL, apR);
+    const Real pL = Real(0.5) * (amL + apL), pR = Real(0.5) * (amR + apR);
+    wl[P] = pL;
+    wr[P] = pR;
+    wl[UN] = (apL - amL) * iz2;
+    wr[UN] = (apR - amR) * iz2;
+#pragma unroll
+    for (int k = 0; k < ND; k++) {
+        Real eL, eR;
+        both([&](int s) { return st(s, k) - g[k] * st(s, P); }, eL, eR);
+        wl[k] = eL + g[k] * pL;
+        wr[k] = eR + g[k] * pR;
+    }
+    both([&](int s) { return st(s, T1); }, wl[T1], wr[T1]);
+    both([&](int s) { return st(s, T2); }, wl[T2], wr[T2]);
+    if constexpr (MODEL == DIM) both([&](int s) { return st(s, 6); }, wl[6], wr[6]);
+}
+
 // ---------------------------------------------------------------- HLLC
 // Face normal to direction DIR.  wl, wr: primitive states.  F: flux F^c in
 // the global frame; uh: upwinded normal velocity u^HLLC.  Wave speeds:

@@ -114,7 +114,7 @@ struct Tile {
 };
 
 // One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
-template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
 __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
 {
     using L = Layout<MODEL>;
@@ -176,11 +176,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     };
 
     // register window W(s-3 .. s+2) of the own column
-    Real win[6][NC];
+    constexpr int NWIN = CHAR ? 7 : 6, WO = CHAR ? 1 : 0;  // characteristic faces need s-4 .. s+2
+    Real win[NWIN][NC];
     const int s_begin = VISC ? z0 - 2 : z0;
 #pragma unroll
-    for (int q = 0; q < 5; q++) {
-        if (has_cell) load_w(gx, gy, s_begin - 3 + q, win[q]);
+    for (int q = 0; q < NWIN - 1; q++) {
+        if (has_cell) load_w(gx, gy, s_begin - 3 - WO + q, win[q]);
         else
 #pragma unroll
             for (int f = 0; f < NC; f++) win[q][f] = Real(1);
@@ -217,7 +218,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         else
 #pragma unroll
             for (int f = 0; f < NC; f++) raw[f] = Real(1);
-        if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
+        if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
         const bool xy = (s >= z0) && (s < z1);
         const bool need_plane = xy || (VISC && s >= z0 - 2);
         Real accC[NC];
@@ -265,9 +266,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
             __syncthreads();
             if (!FV_EARLY_HALO && has_halo) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
-            if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
+            if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
-            if (has_cell) stage_w(tx, ty, win[3]);
+            if (has_cell) stage_w(tx, ty, win[3 + WO]);
             if (has_halo) {
                 Real w[NC];
                 cons_to_prim<Real, MODEL>(mat, hu, w);
@@ -281,7 +282,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         Real dz[3];
 #pragma unroll
                         for (int c = 0; c < 3; c++)
-                            dz[c] = dcell(win[1][V + c], win[2][V + c], win[4][V + c], win[5][V + c], i12);
+                            dz[c] = dcell(win[1 + WO][V + c], win[2 + WO][V + c], win[4 + WO][V + c], win[5 + WO][V + c], i12);
                         DZX[0 * TL::RX + ty * (BX + 4) + tx + 2] = dz[0];
                         DZX[1 * TL::RX + ty * (BX + 4) + tx + 2] = dz[2];
                         DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
@@ -340,15 +341,18 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
         }
 
-        if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[5]);
+        if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
 
         // ---- z work of the own column (registers only): finalises cell s-2
         if (has_cell && s >= z0) {
-            // reconstruction of cell s-1 from W(s-3 .. s+1) = win[0..4]
+            // primitive variables: the reconstruction of cell s-1 from W(s-3 .. s+1) gives
+            // its face values at s-3/2 (used now) and s-1/2 (carried to the next step)
             Real vm_new[NC], vp[NC];
+            if constexpr (!CHAR) {
 #pragma unroll
-            for (int m = 0; m < NC; m++)
-                weno5z_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], weps, vm_new[m], vp[m]);
+                for (int m = 0; m < NC; m++)
+                    weno5z_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], weps, vm_new[m], vp[m]);
+            }
             if (s >= z0 + 1) {
                 // z face s-3/2 between cells s-2 (win[1]) and s-1 (win[2])
                 Real Fd[4];
@@ -358,12 +362,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     Real dn[4], vf[3];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const Real q0 = win[0][V + c], q1 = win[1][V + c], q2 = win[2][V + c], q3 = win[3][V + c];
+                        const Real q0 = win[WO][V + c], q1 = win[1 + WO][V + c], q2 = win[2 + WO][V + c], q3 = win[3 + WO][V + c];
                         dn[c] = dface(q0, q1, q2, q3, i24);
                         vf[c] = ifc(q0, q1, q2, q3);
                     }
-                    dn[3] = dface(win[0][P] * rcp(win[0][0]), win[1][P] * rcp(win[1][0]), win[2][P] * rcp(win[2][0]),
-                                  win[3][P] * rcp(win[3][0]), i24);
+                    dn[3] = dface(win[WO][P] * rcp(win[WO][0]), win[1 + WO][P] * rcp(win[1 + WO][0]),
+                                  win[2 + WO][P] * rcp(win[2 + WO][0]), win[3 + WO][P] * rcp(win[3 + WO][0]), i24);
                     const Real g_xw = ifc(Dc[0][0], Dc[1][0], Dc[2][0], Dnew[0]);  // dw/dx
                     const Real g_yw = ifc(Dc[0][2], Dc[1][2], Dc[2][2], Dnew[2]);  // dw/dy
                     const Real g_xu = ifc(Dc[0][1], Dc[1][1], Dc[2][1], Dnew[1]);  // du/dx
@@ -372,21 +376,26 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     __builtin_amdgcn_sched_barrier(0);  // keep the two flux parts from interleaving (registers)
                 }
                 Real wl[NC], wr[NC], F[NC], uh;
+                if constexpr (CHAR) {
+                    // characteristic variables of the face's frozen state, stencil s-4 .. s+1
+                    char_face_states<Real, MODEL, 2>(mat, [&](int q, int m) { return win[q][m]; }, weps, wl, wr);
+                } else {
 #pragma unroll
-                for (int m = 0; m < NC; m++) {
-                    wl[m] = vminus[m];
-                    wr[m] = vp[m];
+                    for (int m = 0; m < NC; m++) {
+                        wl[m] = vminus[m];
+                        wr[m] = vp[m];
+                    }
                 }
                 if constexpr (POS) {
                     if (inadmissible_w<Real, MODEL>(mat, tol, wl))
 #pragma unroll
-                        for (int m = 0; m < NC; m++) wl[m] = win[1][m];
+                        for (int m = 0; m < NC; m++) wl[m] = win[1 + WO][m];
                     if (inadmissible_w<Real, MODEL>(mat, tol, wr))
 #pragma unroll
-                        for (int m = 0; m < NC; m++) wr[m] = win[2][m];
+                        for (int m = 0; m < NC; m++) wr[m] = win[2 + WO][m];
                     hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
-                    if (flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1], win[2], F, uh, lamz))
-                        hllc<Real, MODEL, 2>(mat, win[1], win[2], F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1 + WO], win[2 + WO], F, uh, lamz))
+                        hllc<Real, MODEL, 2>(mat, win[1 + WO], win[2 + WO], F, uh);
                 } else {
                     hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
                 }
@@ -408,7 +417,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
 #pragma unroll
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
                     }
-                    if constexpr (MODEL == DIM) r[6] += win[1][6] * (srcA + (uh - uhzl) * idz);
+                    if constexpr (MODEL == DIM) r[6] += win[1 + WO][6] * (srcA + (uh - uhzl) * idz);
                     Real unew[NC];
                     if (!FV_PREFETCH_RK && a.mode != 0) {
 #pragma unroll
@@ -424,8 +433,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
                 uhzl = uh;
             }
+            if constexpr (!CHAR) {
 #pragma unroll
-            for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];
+                for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];
+            }
         }
 
         if (xy) {
@@ -433,7 +444,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
             Real* FL = FB;
             Real* FR = FB + NC * TL::NFX;
-            if constexpr (FV_RECON_ITEMS) {
+            if constexpr (CHAR) {
+                // one task per x face: characteristic reconstruction of both face states
+                for (int t = rt; t < TL::NFX; t += NT) {
+                    const int j = t / (BX + 1), f = t - j * (BX + 1);
+                    Real wl[NC], wr[NC];
+                    char_face_states<Real, MODEL, 0>(mat, [&](int q, int m) { return wp(m, f - 3 + q, j); }, weps, wl,
+                                                     wr);
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        FL[m * TL::NFX + t] = wl[m];
+                        FR[m * TL::NFX + t] = wr[m];
+                    }
+                }
+            } else if constexpr (FV_RECON_ITEMS) {
                 // one item = one component of one cell; consecutive lanes take consecutive cells
                 constexpr int NTX = (BX + 2) * BY;
                 auto item = [&](int it) {
@@ -528,7 +552,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
             Real* GL = FB;
             Real* GR = FB + NC * TL::NFY;
-            if constexpr (FV_RECON_ITEMS) {
+            if constexpr (CHAR) {
+                for (int t = rt; t < TL::NFY; t += NT) {
+                    const int f = t / BX, i = t - f * BX;
+                    Real wl[NC], wr[NC];
+                    char_face_states<Real, MODEL, 1>(mat, [&](int q, int m) { return wp(m, i, f - 3 + q); }, weps, wl,
+                                                     wr);
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        GL[m * TL::NFY + t] = wl[m];
+                        GR[m * TL::NFY + t] = wr[m];
+                    }
+                }
+            } else if constexpr (FV_RECON_ITEMS) {
                 constexpr int NTY = BX * (BY + 2);
                 auto item = [&](int it) {
                     const int m = it / NTY, t = it - m * NTY;
@@ -639,7 +675,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
         }
 #pragma unroll
-        for (int q = 0; q < 5; q++)
+        for (int q = 0; q < NWIN - 1; q++)
 #pragma unroll
             for (int f = 0; f < NC; f++) win[q][f] = win[q + 1][f];
     }
@@ -659,16 +695,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 }
 
-template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 #if FV_KERNARG_INPLACE
     // the argument block read in place from the kernel-argument segment
     const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
-    stage_body<Real, MODEL, POS, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, CHAR, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
 #else
-    stage_body<Real, MODEL, POS, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, CHAR, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
 #endif
 }
 
@@ -688,23 +724,24 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU)
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stage_body<Real, MODEL, POS, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+    stage_body<Real, MODEL, POS, false, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     using TL = Tile<Real, MODEL, BX, BY, NTH>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, BX, BY, NTH>,
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, CHAR, BX, BY, NTH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds, st, args);
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, CHAR, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds, st,
+                       args);
     return hipGetLastError();
 }
 
@@ -717,8 +754,12 @@ size_t stage_lds_bytes()
 template <typename Real, int MODEL>
 static hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    if (args.positivity) return launch_tile<Real, MODEL, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
-    return launch_tile<Real, MODEL, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    if (args.recon == 1) {
+        if (args.positivity) return launch_tile<Real, MODEL, true, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+        return launch_tile<Real, MODEL, false, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    }
+    if (args.positivity) return launch_tile<Real, MODEL, true, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_tile<Real, MODEL, false, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
 template <typename Real, int MODEL, bool POS>

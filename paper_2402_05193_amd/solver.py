@@ -43,7 +43,7 @@ class _Cfg(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("model", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 6),
-        ("positivity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("positivity", ctypes.c_int32), ("recon", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
         ("gamma1", ctypes.c_double), ("pinf1", ctypes.c_double),
         ("gamma2", ctypes.c_double), ("pinf2", ctypes.c_double),
@@ -83,6 +83,7 @@ class Config:
     eps_alpha: float = 0.0
     weno_eps: float = 0.0
     cfl: float = 0.5
+    recon: int = 0          # 0: primitive variables, 1: characteristic variables
 
     @property
     def ncomp(self) -> int:
@@ -107,7 +108,7 @@ class Config:
         c.model, c.dtype = self.model, self.dtype
         for i, b in enumerate(self.bc):
             c.bc[i] = int(b)
-        c.positivity, c.reserved = self.positivity, 0
+        c.positivity, c.recon = self.positivity, self.recon
         c.dx, c.dy, c.dz = self.dx, self.dy, self.dz
         c.gamma1, c.pinf1, c.gamma2, c.pinf2 = self.gamma1, self.pinf1, self.gamma2, self.pinf2
         c.mu, c.prandtl = self.mu, self.prandtl
