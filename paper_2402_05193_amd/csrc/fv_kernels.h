@@ -36,6 +36,9 @@
 #ifndef FV_RECON_ITEMS
 #define FV_RECON_ITEMS 1
 #endif
+#ifndef FV_SKIP_PLANE_BARRIER
+#define FV_SKIP_PLANE_BARRIER 1
+#endif
 #ifndef FV_KERNARG_INPLACE
 #define FV_KERNARG_INPLACE 1
 #endif

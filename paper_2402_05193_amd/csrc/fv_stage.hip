@@ -264,7 +264,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 }
                 if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
             }
-            __syncthreads();
+            // the plane buffer is overwritten below: after a step with x/y phases their
+            // barriers already ordered every read of it; after a warm-up step (only the
+            // in-plane derivatives read it) a barrier is needed here
+            const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
+            if (!FV_SKIP_PLANE_BARRIER || !prev_xy) __syncthreads();
             if (!FV_EARLY_HALO && has_halo) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
             if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
