@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define FV_ABI_VERSION 1
+#define FV_ABI_VERSION 2
 
 enum fv_model { FV_EULER = 0, FV_NS = 1, FV_DIM = 2 };
 enum fv_dtype { FV_F64 = 0, FV_F32 = 1 };
@@ -98,6 +98,15 @@ typedef struct fv_config {
     double eps_rho, eps_rhoc2, eps_alpha; /* limiter tolerances (0: default) */
     double weno_eps;     /* WENO-Z epsilon (0: default)                    */
     double cfl;          /* CFL number used by advance/compute_dt, > 0     */
+    int32_t visc_law;    /* dynamic viscosity (Sec. 2.5), FV_NS only: 0 constant mu;
+                            1 power law mu (T/T_ref)^0.7; 2 Sutherland
+                            mu (T/T_ref)^1.5 (T_ref + C)/(T + C); mu = the value at
+                            T_ref.  Faces use the temperature interpolated to the face;
+                            conductivity from the constant Prandtl number          */
+    int32_t reserved;    /* must be 0                                      */
+    double T_ref;        /* reference temperature of the law, > 0 when visc_law != 0 */
+    double sutherland;   /* Sutherland's constant C, >= 0                  */
+    double gas_R;        /* specific gas constant in T = p / (rho R); 0 selects 1 */
 } fv_config;
 
 /* Result of check_state. */

@@ -44,6 +44,8 @@ class _Cfg(ctypes.Structure):
         ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
+        ("visc_law", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
     ]
 
 
@@ -70,6 +72,10 @@ class Config:
     eps_alpha: float = 1e-12
     weno_eps: float = 1e-40
     recon: int = 0                # 0: primitive variables, 1: characteristic variables
+    visc_law: int = 0             # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
+    T_ref: float = 1.0
+    sutherland: float = 0.0
+    gas_R: float = 1.0
 
     @property
     def ncomp(self) -> int:
@@ -95,6 +101,8 @@ class Config:
         c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
         c.weno_eps = self.weno_eps
         c.recon = self.recon
+        c.visc_law = self.visc_law
+        c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
         return c
 
 

@@ -61,6 +61,11 @@ typedef struct {
     double mu, prandtl;
     double eps_rho, eps_rhoc2, eps_alpha;
     double weno_eps;
+    int32_t visc_law;    /* 0: constant mu; 1: power law; 2: Sutherland (Sec. 2.5) */
+    int32_t pad2_;
+    double T_ref;        /* reference temperature of the viscosity law */
+    double sutherland;   /* Sutherland's constant C */
+    double gas_R;        /* specific gas constant, T = p / (rho R) */
 } orc_cfg;
 
 #define NH 3   /* halo width: WENO5 at face i-1/2 reads cells i-3 .. i+2 */
@@ -428,13 +433,23 @@ static const int DI[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 /* ------------------------------------------------------------------------ */
 
 /* quantity q at a cell: 0,1,2 = velocity components, 3 = temperature T = p/(rho R) */
-static const double R_GAS = 1.0; /* any gas constant: it cancels in lambda dT/dx */
+static double gas_R(const orc_cfg *c) { return c->gas_R > 0.0 ? c->gas_R : 1.0; }
 static double visc_q(const orc_cfg *c, const padded *p, int m, int i, int j, int k)
 {
     int v = vel0(c);
     if (m < 3) return get_q(p, v + m, i, j, k);
     double rho = c->model == M_DIM ? get_q(p, 0, i, j, k) + get_q(p, 1, i, j, k) : get_q(p, 0, i, j, k);
-    return get_q(p, pidx(c), i, j, k) / (rho * R_GAS);
+    return get_q(p, pidx(c), i, j, k) / (rho * gas_R(c));
+}
+
+/* dynamic viscosity at temperature T (Sec. 2.5, material properties): constant,
+ * the power law mu_ref (T/T_ref)^0.7, or Sutherland's law
+ * mu_ref (T/T_ref)^1.5 (T_ref + C)/(T + C); mu_ref = cfg mu */
+static double viscosity(const orc_cfg *c, double T)
+{
+    if (c->visc_law == 1) return c->mu * pow(T / c->T_ref, 0.7);
+    if (c->visc_law == 2) return c->mu * pow(T / c->T_ref, 1.5) * (c->T_ref + c->sutherland) / (T + c->sutherland);
+    return c->mu;
 }
 
 /* 4th-order central derivative of q at a cell centre in direction e:
@@ -466,12 +481,12 @@ static void viscous_flux(const orc_cfg *c, const padded *p, int d, int i, int j,
         cj[s] = j + (s - 1) * o[1];
         ck[s] = k + (s - 1) * o[2];
     }
-    /* gradient g[m][e] = d q_m / d x_e at the face, m = u,v,w,T */
-    double g[4][3], qf[3];
+    /* gradient g[m][e] = d q_m / d x_e at the face, m = u,v,w,T; face values qf */
+    double g[4][3], qf[4];
     for (int m = 0; m < 4; m++) {
         double q[4];
         for (int s = 0; s < 4; s++) q[s] = visc_q(c, p, m, ci[s], cj[s], ck[s]);
-        if (m < 3) qf[m] = interp4(q[0], q[1], q[2], q[3]);
+        qf[m] = interp4(q[0], q[1], q[2], q[3]);
         for (int e = 0; e < 3; e++) {
             if (e == d) {
                 /* normal: (q_{i-1} - 27 q_i + 27 q_{i+1} - q_{i+2}) / (24 h) */
@@ -483,14 +498,15 @@ static void viscous_flux(const orc_cfg *c, const padded *p, int d, int i, int j,
             }
         }
     }
-    double mu = c->mu;
+    /* viscosity and conductivity at the face temperature (constant Prandtl number) */
+    double mu = viscosity(c, qf[3]);
     double divu = g[0][0] + g[1][1] + g[2][2];
     double tau[3];
     for (int e = 0; e < 3; e++) {
         tau[e] = mu * (g[d][e] + g[e][d]);
         if (e == d) tau[e] -= 2.0 / 3.0 * mu * divu;
     }
-    double cp = c->gamma1 * R_GAS / (c->gamma1 - 1.0);
+    double cp = c->gamma1 * gas_R(c) / (c->gamma1 - 1.0);
     double lambda = mu * cp / c->prandtl;
     double qheat = -lambda * g[3][d];
     int v = vel0(c), nc = orc_ncomp(c);
@@ -865,7 +881,8 @@ double orc_dt(const orc_cfg *c, const double *U, double cfl)
             if (t < dtc) dtc = t;
         }
         if (c->model == M_NS && c->mu > 0.0) {
-            double t = 3.0 / 14.0 * w_density(c, w) * hmin * hmin / c->mu;
+            double mu = viscosity(c, w[pidx(c)] / (w_density(c, w) * gas_R(c)));
+            double t = 3.0 / 14.0 * w_density(c, w) * hmin * hmin / mu;
             if (t < dtv) dtv = t;
         }
     }

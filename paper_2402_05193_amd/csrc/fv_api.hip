@@ -49,6 +49,14 @@ int validate(const fv_config* c)
     if (c->model < FV_EULER || c->model > FV_DIM) return fail(FV_EINVAL, "model %d unknown", c->model);
     if (c->dtype != FV_F64 && c->dtype != FV_F32) return fail(FV_EINVAL, "dtype %d unknown", c->dtype);
     if (c->recon != 0 && c->recon != 1) return fail(FV_EINVAL, "recon must be 0 or 1");
+    if (c->reserved != 0) return fail(FV_EINVAL, "reserved must be 0");
+    if (c->visc_law < 0 || c->visc_law > 2) return fail(FV_EINVAL, "visc_law %d unknown", c->visc_law);
+    if (c->visc_law != 0) {
+        if (c->model != FV_NS) return fail(FV_EINVAL, "viscosity laws apply to the viscous model");
+        if (!(c->T_ref > 0)) return fail(FV_EINVAL, "T_ref must be > 0");
+        if (!(c->sutherland >= 0)) return fail(FV_EINVAL, "sutherland must be >= 0");
+    }
+    if (!(c->gas_R >= 0)) return fail(FV_EINVAL, "gas_R must be >= 0");
     const int n3[3] = {c->nx, c->ny, c->nz};
     for (int a = 0; a < 3; a++) {
         for (int s = 0; s < 2; s++) {
@@ -93,6 +101,21 @@ fv::Material<Real> material(const fv_config* c)
     return m;
 }
 
+template <typename Real>
+fv::ViscLaw<Real> visc_law(const fv_config* c)
+{
+    fv::ViscLaw<Real> v;
+    const bool ns = c->model == FV_NS;
+    const double R = c->gas_R > 0 ? c->gas_R : 1.0;
+    v.law = ns ? c->visc_law : 0;
+    v.mu = (Real)(ns ? c->mu : 0.0);
+    v.kfac = (Real)(ns ? c->gamma1 / ((c->gamma1 - 1.0) * c->prandtl) : 0.0);
+    v.inv_th_ref = (Real)(v.law ? 1.0 / (R * c->T_ref) : 0.0);
+    v.th_c = (Real)(R * c->sutherland);
+    v.th_ref_c = (Real)(R * (c->T_ref + c->sutherland));
+    return v;
+}
+
 fv::AuxArgs aux_args(const fv_config* c)
 {
     fv::AuxArgs a;
@@ -106,6 +129,7 @@ fv::AuxArgs aux_args(const fv_config* c)
     a.dz = c->dz;
     a.matd = material<double>(c);
     a.matf = material<float>(c);
+    a.vl = visc_law<double>(c);
     return a;
 }
 
@@ -157,6 +181,8 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.mu = (Real)(c->model == FV_NS ? c->mu : 0.0);
     const double hmin = fmin(c->dx, fmin(c->dy, c->dz));
     a.kvisc = c->model == FV_NS ? (14.0 / 3.0) * c->mu / (hmin * hmin) : 0.0;
+    a.kvisc_h = (14.0 / 3.0) / (hmin * hmin);
+    a.vl = visc_law<Real>(c);
     a.inv_max = nullptr;
     a.kappa = (Real)(c->model == FV_NS ? c->mu * c->gamma1 / ((c->gamma1 - 1.0) * c->prandtl) : 0.0);
     return a;
@@ -683,6 +709,7 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if ((r = check_ptr(U[i], "U")) || (r = check_ptr(ws[i], "ws"))) return fail(r, "member %d: %s", i, last_error());
         if (!(cfgs[i].cfl > 0)) return fail(FV_EINVAL, "member %d: cfl must be > 0", i);
         if (cfgs[i].recon != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use primitive reconstruction", i);
+        if (cfgs[i].visc_law != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use constant viscosity", i);
     }
     // groups in order of first appearance; members keep their order inside a group
     std::vector<BatchGroup> groups;

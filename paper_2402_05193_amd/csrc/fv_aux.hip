@@ -203,7 +203,10 @@ __global__ void __launch_bounds__(AUX_THREADS) inv_dt_kernel(const AuxArgs a, co
         const double s1 = (fabs((double)w[V + 1]) + c) / a.dy;
         const double s2 = (fabs((double)w[V + 2]) + c) / a.dz;
         double t = fmax(s0, fmax(s1, s2));
-        if (MODEL == NS && mu > 0.0) t = fmax(t, mu / (3.0 / 14.0 * rho * hmin * hmin));
+        if (MODEL == NS && mu > 0.0) {
+            const double m = a.vl.law == 0 ? mu : visc_mu(a.vl, (double)w[Layout<MODEL>::P] / rho);
+            t = fmax(t, m / (3.0 / 14.0 * rho * hmin * hmin));
+        }
         if (!(t >= 0.0)) t = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf (dt -> 0)
         v = fmax(v, t);
     }

@@ -73,6 +73,8 @@ struct StageArgs {
     // max_d (|u_d| + c)/dx_d and kvisc / rho, as the bit pattern of a double
     unsigned long long* inv_max;
     double kvisc;        // (14/3) mu / dx_min^2 (0 without viscosity)
+    double kvisc_h;      // (14/3) / dx_min^2 (viscosity laws)
+    ViscLaw<Real> vl;    // viscosity law of the faces (law 0: mu and kappa above)
 };
 
 struct LaunchGeom {
@@ -110,6 +112,7 @@ struct AuxArgs {
     double dx, dy, dz;
     Material<double> matd;
     Material<float> matf;
+    ViscLaw<double> vl;  // viscosity law for the viscous CFL limit
 };
 
 template <typename Real>

@@ -46,6 +46,19 @@ struct Tolerances {
     Real eps_rho, eps_rhoc2, eps_alpha;
 };
 
+// Dynamic viscosity law (Sec. 2.5, material properties), in terms of theta =
+// p / rho = R T: law 0 constant mu; 1 power law mu (T/T_ref)^0.7; 2 Sutherland
+// mu (T/T_ref)^1.5 (T_ref + C)/(T + C).  kfac = gamma/((gamma-1) Pr) gives the
+// heat-flux coefficient kfac mu (constant Prandtl number; R cancels).
+template <typename Real>
+struct ViscLaw {
+    int law;
+    Real mu, kfac;
+    Real inv_th_ref;  // 1/(R T_ref)
+    Real th_c;        // R C
+    Real th_ref_c;    // R (T_ref + C)
+};
+
 // ---------------------------------------------------------------- arithmetic helpers
 // 1/x and 1/sqrt(x) from the hardware estimates (relative error below 2^-24
 // on gfx950, measured) with one third-order correction: for r = 1/x (1 - e),
@@ -488,6 +501,15 @@ __device__ __forceinline__ bool flux_limiter_trips(const Material<Real>& mat, co
 }
 
 // ---------------------------------------------------------------- viscous
+template <typename Real>
+__device__ __forceinline__ Real visc_mu(const ViscLaw<Real>& v, Real theta)
+{
+    if (v.law == 0) return v.mu;
+    const Real x = theta * v.inv_th_ref;  // T / T_ref
+    if (v.law == 1) return v.mu * pow(x, Real(0.7));
+    return v.mu * (x * sqrt_fast(x)) * (v.th_ref_c * rcp(theta + v.th_c));
+}
+
 // 4th-order central stencils:
 //   face normal derivative  ((q_{-1} - q_{+2}) + 27 (q_{+1} - q_0)) / (24 h)
 //   cell derivative         ((q_{-2} - q_{+2}) + 8 (q_{+1} - q_{-1})) / (12 h)

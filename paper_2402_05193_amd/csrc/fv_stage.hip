@@ -70,7 +70,7 @@ __device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long l
 }
 
 // Inverse CFL time step of a conservative state: max(max_d (|u_d| + c)/dx_d, kvisc/rho).
-template <typename Real, int MODEL>
+template <typename Real, int MODEL, bool VLAW>
 __device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Real* u)
 {
     constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V;
@@ -79,7 +79,11 @@ __device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Rea
     const Real ir = rcp(density<Real, MODEL>(w));
     const Real c = sqrt_fast(rhoc2<Real, MODEL>(a.mat, w) * ir);
     Real v = fmax((fabs(w[V]) + c) * a.idx, fmax((fabs(w[V + 1]) + c) * a.idy, (fabs(w[V + 2]) + c) * a.idz));
-    if constexpr (MODEL == NS) v = fmax(v, Real(a.kvisc) * ir);
+    if constexpr (MODEL == NS) {
+        Real kv = Real(a.kvisc);
+        if constexpr (VLAW) kv = visc_mu(a.vl, w[Layout<MODEL>::P] * ir) * Real(a.kvisc_h);
+        v = fmax(v, kv * ir);
+    }
     const double d = (double)v;
     return d >= 0.0 ? d : __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
 }
@@ -114,7 +118,7 @@ struct Tile {
 };
 
 // One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
-template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, bool VLAW, int BX, int BY, int NTH>
 __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
 {
     using L = Layout<MODEL>;
@@ -370,13 +374,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         dn[c] = dface(q0, q1, q2, q3, i24);
                         vf[c] = ifc(q0, q1, q2, q3);
                     }
-                    dn[3] = dface(win[WO][P] * rcp(win[WO][0]), win[1 + WO][P] * rcp(win[1 + WO][0]),
-                                  win[2 + WO][P] * rcp(win[2 + WO][0]), win[3 + WO][P] * rcp(win[3 + WO][0]), i24);
+                    const Real th0 = win[WO][P] * rcp(win[WO][0]), th1 = win[1 + WO][P] * rcp(win[1 + WO][0]);
+                    const Real th2 = win[2 + WO][P] * rcp(win[2 + WO][0]), th3 = win[3 + WO][P] * rcp(win[3 + WO][0]);
+                    dn[3] = dface(th0, th1, th2, th3, i24);
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        muf = visc_mu(a.vl, ifc(th0, th1, th2, th3));
+                        kf = muf * a.vl.kfac;
+                    }
                     const Real g_xw = ifc(Dc[0][0], Dc[1][0], Dc[2][0], Dnew[0]);  // dw/dx
                     const Real g_yw = ifc(Dc[0][2], Dc[1][2], Dc[2][2], Dnew[2]);  // dw/dy
                     const Real g_xu = ifc(Dc[0][1], Dc[1][1], Dc[2][1], Dnew[1]);  // du/dx
                     const Real g_yv = ifc(Dc[0][3], Dc[1][3], Dc[2][3], Dnew[3]);  // dv/dy
-                    viscous_flux_from_gradients<Real, 2>(dn, vf, g_xw, g_yw, g_xu, g_yv, a.mu, a.kappa, Fd);
+                    viscous_flux_from_gradients<Real, 2>(dn, vf, g_xw, g_yw, g_xu, g_yv, muf, kf, Fd);
                     __builtin_amdgcn_sched_barrier(0);  // keep the two flux parts from interleaving (registers)
                 }
                 Real wl[NC], wr[NC], F[NC], uh;
@@ -431,7 +441,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         }
                     }
                     store_cell_impl<Real, NC>(a, q, r, dt, pre_k, pre_n, unew);
-                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL>(a, unew));
+                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, VLAW>(a, unew));
                 }
 #pragma unroll
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
@@ -529,8 +539,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 if constexpr (VISC) {
                     const int r0 = j * (BX + 4) + f;  // region index of cell f-2
                     Real Fd[4];
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        const Real* th = &wp(NC, f - 2, j);
+                        muf = visc_mu(a.vl, ifc(th[0], th[1], th[2], th[3]));
+                        kf = muf * a.vl.kfac;
+                    }
                     viscous_flux_lds<Real, 0>(&wp(V, f - 2, j), &wp(NC, f - 2, j), 1, PLANE, DT + r0, DZX + r0,
-                                              DT + TL::RX + r0, DZX + TL::RX + r0, 1, a.mu, a.kappa, a.inv24dx, Fd);
+                                              DT + TL::RX + r0, DZX + TL::RX + r0, 1, muf, kf, a.inv24dx, Fd);
                     F[V] -= Fd[0];
                     F[V + 1] -= Fd[1];
                     F[V + 2] -= Fd[2];
@@ -636,8 +652,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 if constexpr (VISC) {
                     const int r0 = f * BX + i;  // region index of cell f-2
                     Real Fd[4];
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        const Real* th = &wp(NC, i, f - 2);
+                        muf = visc_mu(a.vl, ifc(th[0], th[PX], th[2 * PX], th[3 * PX]));
+                        kf = muf * a.vl.kfac;
+                    }
                     viscous_flux_lds<Real, 1>(&wp(V, i, f - 2), &wp(NC, i, f - 2), PX, PLANE, DT + r0, DZY + r0,
-                                              DT + TL::RY + r0, DZY + TL::RY + r0, BX, a.mu, a.kappa, a.inv24dy, Fd);
+                                              DT + TL::RY + r0, DZY + TL::RY + r0, BX, muf, kf, a.inv24dy, Fd);
                     F[V] -= Fd[0];
                     F[V + 1] -= Fd[1];
                     F[V + 2] -= Fd[2];
@@ -699,16 +721,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 }
 
-template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, bool VLAW, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 #if FV_KERNARG_INPLACE
     // the argument block read in place from the kernel-argument segment
     const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
-    stage_body<Real, MODEL, POS, CHAR, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, CHAR, VLAW, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
 #else
-    stage_body<Real, MODEL, POS, CHAR, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, CHAR, VLAW, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
 #endif
 }
 
@@ -728,25 +750,36 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU)
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stage_body<Real, MODEL, POS, false, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+    stage_body<Real, MODEL, POS, false, false, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, bool POS, bool CHAR, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, bool CHAR, bool VLAW, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     using TL = Tile<Real, MODEL, BX, BY, NTH>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, CHAR, BX, BY, NTH>,
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, CHAR, VLAW, BX, BY, NTH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, CHAR, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds, st,
-                       args);
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, CHAR, VLAW, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds,
+                       st, args);
     return hipGetLastError();
+}
+
+template <typename Real, int MODEL, bool VLAW>
+static hipError_t launch_variant(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    if (args.recon == 1) {
+        if (args.positivity) return launch_tile<Real, MODEL, true, true, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+        return launch_tile<Real, MODEL, false, true, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    }
+    if (args.positivity) return launch_tile<Real, MODEL, true, false, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_tile<Real, MODEL, false, false, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
 template <typename Real, int MODEL>
@@ -758,12 +791,12 @@ size_t stage_lds_bytes()
 template <typename Real, int MODEL>
 static hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    if (args.recon == 1) {
-        if (args.positivity) return launch_tile<Real, MODEL, true, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
-        return launch_tile<Real, MODEL, false, true, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    // a viscosity law is a separate instantiation (viscous model only): the law's
+    // pow() must not weigh on the constant-viscosity kernel
+    if constexpr (MODEL == NS) {
+        if (args.vl.law != 0) return launch_variant<Real, MODEL, true>(args, g, st);
     }
-    if (args.positivity) return launch_tile<Real, MODEL, true, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
-    return launch_tile<Real, MODEL, false, false, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_variant<Real, MODEL, false>(args, g, st);
 }
 
 template <typename Real, int MODEL, bool POS>

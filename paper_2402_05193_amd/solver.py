@@ -17,7 +17,7 @@ EULER, NS, DIM = 0, 1, 2
 F64, F32 = 0, 1
 PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
 CASE_UNIFORM, CASE_TGV, CASE_RIEMANN, CASE_SBI = 0, 1, 2, 3
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 
@@ -51,6 +51,8 @@ class _Cfg(ctypes.Structure):
         ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("visc_law", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
     ]
 
 
@@ -84,6 +86,10 @@ class Config:
     weno_eps: float = 0.0
     cfl: float = 0.5
     recon: int = 0          # 0: primitive variables, 1: characteristic variables
+    visc_law: int = 0       # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
+    T_ref: float = 1.0
+    sutherland: float = 0.0
+    gas_R: float = 1.0
 
     @property
     def ncomp(self) -> int:
@@ -114,6 +120,8 @@ class Config:
         c.mu, c.prandtl = self.mu, self.prandtl
         c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
         c.weno_eps, c.cfl = self.weno_eps, self.cfl
+        c.visc_law, c.reserved = self.visc_law, 0
+        c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
         return c
 
 

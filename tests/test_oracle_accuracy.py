@@ -201,8 +201,9 @@ def test_viscous_shear_and_heat_exact_for_quadratics():
     assert np.abs(R2[0][0, inner, :]).max() < 1e-12
 
 
-def _viscous_part(n):
-    """R_NS - R_Euler on a smooth periodic field versus exact face fluxes."""
+def _viscous_part(n, law=0, T_ref=1.1, C=0.4):
+    """R_NS - R_Euler on a smooth periodic field versus exact face fluxes
+    (viscosity constant, or the power / Sutherland law of the temperature)."""
     L = 2 * math.pi
     h = L / n
     mu, pr, g = 0.05, 0.72, 1.4
@@ -220,7 +221,8 @@ def _viscous_part(n):
     W[1] = fields["u"](X, Y, Z)
     W[2] = fields["v"](X, Y, Z)
     W[3] = fields["w"](X, Y, Z)
-    ns = O.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=O.NS, mu=mu, prandtl=pr, gamma1=g)
+    ns = O.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=O.NS, mu=mu, prandtl=pr, gamma1=g, visc_law=law,
+                  T_ref=T_ref, sutherland=C)
     eu = O.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=O.EULER, gamma1=g)
     U = O.prim_to_cons(ns, W)
     Rv = O.rhs(ns, U) - O.rhs(eu, U)
@@ -232,6 +234,11 @@ def _viscous_part(n):
     vel = [S["u"], S["v"], S["w"]]
     X3 = [x, y, z]
     div = sum(sp.diff(vel[k], X3[k]) for k in range(3))
+    mu_ref = mu
+    if law == 1:
+        mu = mu_ref * (S["T"] / T_ref) ** sp.Rational(7, 10)
+    elif law == 2:
+        mu = mu_ref * (S["T"] / T_ref) ** sp.Rational(3, 2) * (T_ref + C) / (S["T"] + C)
     lam = mu * (g / (g - 1)) / pr
     ref = np.zeros((5, n, n, n))
     for d in range(3):
@@ -248,6 +255,38 @@ def _viscous_part(n):
     return np.abs(Rv[1:] - ref[1:]).max()
 
 
-def test_viscous_flux_fourth_order_against_exact_fluxes():
-    e1, e2 = _viscous_part(16), _viscous_part(32)
+@pytest.mark.parametrize("law", [0, 1, 2])
+def test_viscous_flux_fourth_order_against_exact_fluxes(law):
+    """4th order for constant viscosity and for the power and Sutherland laws
+    (Sec. 2.5) evaluated at the interpolated face temperature."""
+    e1, e2 = _viscous_part(16, law), _viscous_part(32, law)
     assert math.log2(e1 / e2) > 3.6, (e1, e2)
+
+
+def test_viscosity_laws_reduce_to_constant_at_reference_temperature():
+    """With T = T_ref everywhere both laws give mu_ref: R equals the constant-mu R."""
+    case = WL.smooth_random(10, 9, 8, model=O.NS, seed=6, mu=0.03)
+    W = case.W.copy()
+    W[4] = 1.7 * W[0]          # p = rho R T_ref with R = 1, T_ref = 1.7
+    base = O.Config(**case.cfg_kwargs())
+    U = O.prim_to_cons(base, W)
+    R0 = O.rhs(base, U)
+    for law in (1, 2):
+        c = O.Config(**case.cfg_kwargs(), visc_law=law, T_ref=1.7, sutherland=0.5)
+        assert np.abs(O.rhs(c, U) - R0).max() <= 1e-14 * np.abs(R0).max()
+
+
+def test_cfl_viscous_limit_uses_the_cell_viscosity():
+    case = WL.smooth_random(6, 5, 4, model=O.NS, seed=2, mu=5.0)
+    c = O.Config(**case.cfg_kwargs(), visc_law=2, T_ref=0.8, sutherland=0.3, gas_R=1.3)
+    U = O.prim_to_cons(c, case.W)
+    W = case.W
+    rho, p = W[0], W[4]
+    T = p / (rho * 1.3)
+    mu = 5.0 * (T / 0.8) ** 1.5 * (0.8 + 0.3) / (T + 0.3)
+    cs = np.sqrt(1.4 * p / rho)
+    h = min(c.dx, c.dy, c.dz)
+    dtc = min((hd / (np.abs(W[1 + d]) + cs)).min() for d, hd in enumerate((c.dx, c.dy, c.dz)))
+    dtv = (3.0 / 14.0 * rho * h * h / mu).min()
+    assert abs(O.compute_dt(c, U, 0.5) - 0.5 * min(dtc, dtv)) <= 1e-14 * dtv
+    assert dtv < dtc   # the viscous limit is the active one here
