@@ -7,9 +7,10 @@
 // conditions by index mapping, as the stage kernel reads them), the two WENO
 // face states and the HLLC flux, then pulls the face cotangent
 //   Fbar_f = (Rbar_f - Rbar_{f-1}) / h        (R_i = -(F_{i+1/2} - F_{i-1/2}) / h)
-// back through HLLC, WENO5-Z and the U -> W map with forward-mode tangents of
-// the same device functions (fv_dual.h), and adds the six cells' cotangents to
-// Ubar with atomic adds.  The order of the atomic additions is not fixed, so
+// back through HLLC (forward-mode tangents of the same device function,
+// fv_dual.h, one per face-state input), WENO5-Z and the U -> W map (reverse
+// sweeps written out below), and adds the six cells' cotangents to Ubar with
+// atomic adds.  The order of the atomic additions is not fixed, so
 // the result is reproducible to round-off, not bitwise.
 #include <hip/hip_runtime.h>
 
@@ -23,6 +24,63 @@ namespace {
 constexpr int ADJ_THREADS = 128;
 
 using D = Dual<double>;
+
+// Reverse sweep of weno5z_one: adds vb * d v / d(a, b, c, d, e) to g[0..4].
+// The forward steps are those of weno5z_one (fv_physics.h): smoothness
+// indicators, the WENO-Z factors g_k = 1 + tau/(beta_k + eps), weights scaled
+// by 10 (1, 6, 3) g_k, candidate values scaled by 6, v = N / D.
+__device__ __forceinline__ void weno5z_one_vjp(double a, double b, double c, double d, double e, double eps,
+                                               double vb, double* g)
+{
+    const double k13 = 13.0 / 12.0, q = 0.25;
+    const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, s1 = b - d;
+    const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+    const double b0 = k13 * t0 * t0 + q * s0 * s0;
+    const double b1 = k13 * t1 * t1 + q * s1 * s1;
+    const double b2 = k13 * t2 * t2 + q * s2 * s2;
+    const double diff = b0 - b2;
+    const double tau = ::fabs(diff);
+    const double r0 = rcp(b0 + eps), r1 = rcp(b1 + eps), r2 = rcp(b2 + eps);
+    const double al0 = 1.0 + tau * r0, al1 = 6.0 * (1.0 + tau * r1), al2 = 3.0 * (1.0 + tau * r2);
+    const double p0 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double p1 = -b + 5.0 * c + 2.0 * d;
+    const double p2 = 2.0 * c + 5.0 * d - e;
+    const double iD = rcp(6.0 * (al0 + al1 + al2));
+    const double v = (al0 * p0 + al1 * p1 + al2 * p2) * iD;
+    // reverse
+    const double Nb = vb * iD;
+    const double Db6 = -6.0 * vb * v * iD;  // 6 * dL/dD
+    const double ab0 = Nb * p0 + Db6, ab1 = Nb * p1 + Db6, ab2 = Nb * p2 + Db6;
+    const double pb0 = Nb * al0, pb1 = Nb * al1, pb2 = Nb * al2;
+    const double gb0 = ab0, gb1 = 6.0 * ab1, gb2 = 3.0 * ab2;  // dL/d(1 + tau r_k)
+    const double taub = gb0 * r0 + gb1 * r1 + gb2 * r2;
+    const double sg = diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0);
+    const double bb0 = -gb0 * tau * r0 * r0 + sg * taub;
+    const double bb1 = -gb1 * tau * r1 * r1;
+    const double bb2 = -gb2 * tau * r2 * r2 - sg * taub;
+    const double tb0 = 2.0 * k13 * t0 * bb0, sb0 = 2.0 * q * s0 * bb0;
+    const double tb1 = 2.0 * k13 * t1 * bb1, sb1 = 2.0 * q * s1 * bb1;
+    const double tb2 = 2.0 * k13 * t2 * bb2, sb2 = 2.0 * q * s2 * bb2;
+    g[0] += 2.0 * pb0 + tb0 + sb0;
+    g[1] += -7.0 * pb0 - pb1 - 2.0 * tb0 - 4.0 * sb0 + tb1 + sb1;
+    g[2] += 11.0 * pb0 + 5.0 * pb1 + 2.0 * pb2 + tb0 + 3.0 * sb0 - 2.0 * tb1 + tb2 + 3.0 * sb2;
+    g[3] += 2.0 * pb1 + 5.0 * pb2 + tb1 - sb1 - 2.0 * tb2 - 4.0 * sb2;
+    g[4] += -pb2 + tb2 + sb2;
+}
+
+// Reverse sweep of the single-phase U -> W map: Ub = (dW/dU)^T Wb.
+__device__ __forceinline__ void cons_to_prim_vjp(const Material<double>& mat, const double* w, const double* wb,
+                                                 double* ub)
+{
+    const double ir = rcp(w[0]);
+    const double gm1 = mat.gm1;
+    const double ke = 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    ub[0] = wb[0] - (wb[1] * w[1] + wb[2] * w[2] + wb[3] * w[3]) * ir + wb[4] * gm1 * ke;
+#pragma unroll
+    for (int i = 0; i < 3; i++) ub[1 + i] = wb[1 + i] * ir - wb[4] * gm1 * w[1 + i];
+    ub[4] = wb[4] * gm1;
+}
 
 template <int DIR>
 __global__ void __launch_bounds__(ADJ_THREADS) face_adjoint_kernel(const AdjointArgs a, const double* __restrict__ U,
@@ -81,7 +139,8 @@ __global__ void __launch_bounds__(ADJ_THREADS) face_adjoint_kernel(const Adjoint
         if (f >= 1) v -= Rbar[m * a.ncell + base + (f - 1) * stride];
         g[m] = v * a.ih;
     }
-    // face states: left = v^- of cell f-1 (stencil slots 0..4), right = v^+ of cell f (slots 1..5)
+    // face states: left = v^- of cell f-1 (stencil slots 0..4), right = v^+ of cell f (slots
+    // 1..5, the mirrored stencil); the same values as the stage kernel's pair reconstruction
     double wl[NC], wr[NC];
 #pragma unroll
     for (int m = 0; m < NC; m++) {
@@ -102,13 +161,13 @@ __global__ void __launch_bounds__(ADJ_THREADS) face_adjoint_kernel(const Adjoint
             dr[m] = D(wr[m], jdx == NC + m ? 1.0 : 0.0);
         }
         hllc<D, EULER, DIR>(dmat, dl, dr, F, uh);
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
-        for (int m = 0; m < NC; m++) s += g[m] * F[m].d;
-        if (jdx < NC) wlb[jdx] = s;
-        else wrb[jdx - NC] = s;
+        for (int m = 0; m < NC; m++) sacc += g[m] * F[m].d;
+        if (jdx < NC) wlb[jdx] = sacc;
+        else wrb[jdx - NC] = sacc;
     }
-    // WENO5-Z: cotangents of the stencil's primitive states
+    // WENO5-Z: cotangents of the stencil's primitive states (reverse sweeps)
     double wb[6][NC];
 #pragma unroll
     for (int s = 0; s < 6; s++)
@@ -116,41 +175,20 @@ __global__ void __launch_bounds__(ADJ_THREADS) face_adjoint_kernel(const Adjoint
         for (int m = 0; m < NC; m++) wb[s][m] = 0.0;
 #pragma unroll
     for (int m = 0; m < NC; m++) {
-#pragma unroll 1
-        for (int k = 0; k < 5; k++) {
-            D st[6];
+        double gl[5] = {0, 0, 0, 0, 0}, gr[5] = {0, 0, 0, 0, 0};
+        weno5z_one_vjp(w[0][m], w[1][m], w[2][m], w[3][m], w[4][m], a.weps, wlb[m], gl);
+        weno5z_one_vjp(w[5][m], w[4][m], w[3][m], w[2][m], w[1][m], a.weps, wrb[m], gr);
 #pragma unroll
-            for (int s = 0; s < 6; s++) st[s] = D(w[s][m], 0.0);
-            D vm, vp, y0, y1;
-            // tangent at slot k of the left stencil and at slot k+1 of the right one
-            st[k].d = 1.0;
-            weno5z_pair(st[0], st[1], st[2], st[3], st[4], D(a.weps), vm, y0);
-            st[k].d = 0.0;
-            st[k + 1].d = 1.0;
-            weno5z_pair(st[1], st[2], st[3], st[4], st[5], D(a.weps), y1, vp);
-            wb[k][m] += wlb[m] * vm.d;
-            wb[k + 1][m] += wrb[m] * vp.d;
+        for (int k = 0; k < 5; k++) {
+            wb[k][m] += gl[k];
+            wb[5 - k][m] += gr[k];
         }
     }
-    // U -> W: cotangents of the conservative states, then the boundary mapping
+    // U -> W, then the boundary mapping
 #pragma unroll
     for (int s = 0; s < 6; s++) {
-        double u[NC];
-#pragma unroll
-        for (int m = 0; m < NC; m++) u[m] = U[m * a.ncell + q[s]];
-        if (flip[s]) u[V + DIR] = -u[V + DIR];
         double ub[NC];
-#pragma unroll 1
-        for (int jdx = 0; jdx < NC; jdx++) {
-            D du[NC], dw[NC];
-#pragma unroll
-            for (int m = 0; m < NC; m++) du[m] = D(u[m], jdx == m ? 1.0 : 0.0);
-            cons_to_prim<D, EULER>(dmat, du, dw);
-            double sacc = 0.0;
-#pragma unroll
-            for (int m = 0; m < NC; m++) sacc += wb[s][m] * dw[m].d;
-            ub[jdx] = sacc;
-        }
+        cons_to_prim_vjp(mat, w[s], wb[s], ub);
         if (flip[s]) ub[V + DIR] = -ub[V + DIR];
 #pragma unroll
         for (int m = 0; m < NC; m++) atomicAdd(&Ubar[m * a.ncell + q[s]], ub[m]);
