@@ -44,7 +44,7 @@ class _Cfg(ctypes.Structure):
         ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
-        ("visc_law", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("visc_law", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
     ]
 
@@ -73,6 +73,7 @@ class Config:
     weno_eps: float = 1e-40
     recon: int = 0                # 0: primitive variables, 1: characteristic variables
     visc_law: int = 0             # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
+    scheme: int = 0               # 0: WENO5-Z, 1: TENO6-A (Sec. 3.2 step 3)
     T_ref: float = 1.0
     sutherland: float = 0.0
     gas_R: float = 1.0
@@ -102,6 +103,7 @@ class Config:
         c.weno_eps = self.weno_eps
         c.recon = self.recon
         c.visc_law = self.visc_law
+        c.scheme = self.scheme
         c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
         return c
 
@@ -119,6 +121,8 @@ def lib():
         L.orc_cons_to_prim.argtypes = [cp, dp, dp]
         L.orc_weno5z.argtypes = [ctypes.c_double] * 6
         L.orc_weno5z.restype = ctypes.c_double
+        L.orc_teno6a_parts.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_teno6a_parts.restype = ctypes.c_double
         L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
         L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
         L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double]
@@ -166,6 +170,22 @@ def cons_to_prim(cfg: Config, U) -> np.ndarray:
 
 def weno5z(a, b, c, d, e, eps=1e-40) -> float:
     return lib().orc_weno5z(a, b, c, d, e, eps)
+
+
+TENO_PARTS = ("beta0", "beta1", "beta2", "beta3", "beta6", "tau6", "CT", "delta0", "delta1", "delta2", "delta3",
+              "omega0", "omega1", "omega2", "omega3")
+
+
+def teno6a(v, eps=1e-40, parts=False):
+    """Left-biased TENO6-A value at x_{i+1/2} from v_{i-2..i+3}; with parts, also
+    the intermediate quantities named in TENO_PARTS."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (6,)
+    out = np.zeros(len(TENO_PARTS))
+    val = lib().orc_teno6a_parts(_dp(v), eps, _dp(out))
+    if parts:
+        return val, dict(zip(TENO_PARTS, out))
+    return val
 
 
 def hllc(cfg: Config, d: int, WL, WR):

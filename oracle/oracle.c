@@ -9,8 +9,8 @@
  * Style: straightforward, slow, materialised arrays.  Every function follows
  * one passage of the paper (cited by section / equation), in the paper's
  * order: pad with boundary conditions (Sec. 3.1), primitive variables
- * (Sec. 2.1, 2.3, 2.4), per direction and face: WENO5-Z reconstruction
- * (Sec. 3.2 step 3), interpolation limiter (Sec. 3.3 item 1), HLLC flux and
+ * (Sec. 2.1, 2.3, 2.4), per direction and face: WENO5-Z or TENO6-A
+ * reconstruction (Sec. 3.2 step 3), interpolation limiter (Sec. 3.3 item 1), HLLC flux and
  * upwinded normal velocity (Sec. 3.2 step 6, Appendix "HLLC approximate
  * Riemann solver"), flux limiter (Sec. 3.3 item 2), central viscous flux
  * (Sec. 2.1 Eq. dissipative_flux, newtonian_shear_stress), then the flux
@@ -29,7 +29,12 @@
  *    tangential derivative at cell centres then interpolated);
  *  - the flux limiter's pseudo-time state is the split forward-Euler state
  *    U_i -/+ 2 D (dt/dx) (F_face - F(U_i));
- *  - CFL: dt = CFL * min(min_d dx_d/(|u_d|+c), (3/14) rho dx_min^2 / mu).
+ *  - CFL: dt = CFL * min(min_d dx_d/(|u_d|+c), (3/14) rho dx_min^2 / mu);
+ *  - TENO6-A: the paper fixes its stencils (figure of the reconstruction
+ *    schematic) and defers its weights to the cited scheme; this oracle takes
+ *    Jiang-Shu indicators, tau_6 = |beta_6 - (beta_0 + 4 beta_1 + beta_2)/6|,
+ *    C = 1, q = 6, the adaptive cut-off with a1 = 10.5, a2 = 3.5, C_r = 0.17,
+ *    xi = 1e-3, and the sixth-order linear weights (see orc_teno6a_parts).
  *
  * Operand order in a few places is chosen so that the result of a mirrored
  * input is the exact mirror image (e.g. the s* numerator is formed as
@@ -62,7 +67,7 @@ typedef struct {
     double eps_rho, eps_rhoc2, eps_alpha;
     double weno_eps;
     int32_t visc_law;    /* 0: constant mu; 1: power law; 2: Sutherland (Sec. 2.5) */
-    int32_t pad2_;
+    int32_t scheme;      /* 0: WENO5-Z, 1: TENO6-A (Sec. 3.2 step 3) */
     double T_ref;        /* reference temperature of the viscosity law */
     double sutherland;   /* Sutherland's constant C */
     double gas_R;        /* specific gas constant, T = p / (rho R) */
@@ -253,6 +258,131 @@ double orc_weno5z(double a, double b, double c, double d, double e, double eps)
     double a2 = 0.3 * (1.0 + tau / (b2 + eps));
     double s = a0 + a1 + a2;
     return (a0 / s) * p0 + (a1 / s) * p1 + (a2 / s) * p2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* TENO6-A (Sec. 3.2 step 3: the six-point targeted ENO scheme with adaptive */
+/* dissipation that the paper cites; constants are this oracle's reading,    */
+/* the paper prints none).  Left-biased value at x_{i+1/2} from              */
+/* v[s] = v_{i-2+s}, s = 0..5.  Candidate stencils as in the figure of the   */
+/* reconstruction schematic: S0 = {i-2,i-1,i}, S1 = {i-1,i,i+1},             */
+/* S2 = {i,i+1,i+2}, S3 = {i,i+1,i+2,i+3}.                                   */
+/*                                                                           */
+/* 1. p_k: the polynomial of degree r_k - 1 whose cell averages on S_k are   */
+/*    the data, evaluated at the face.                                      */
+/* 2. beta_k: Jiang-Shu smoothness indicator of that polynomial (sum over   */
+/*    its derivatives l >= 1 of dx^(2l-1) times the integral over cell i of  */
+/*    the squared derivative); beta_6 the same for the degree-5 polynomial   */
+/*    on all six cells.                                                     */
+/* 3. tau_6 = |beta_6 - (beta_0 + 4 beta_1 + beta_2) / 6|, the combination  */
+/*    that agrees with beta_6 through the fifth power of dx on smooth data.  */
+/* 4. gamma_k = (C + tau_6 / (beta_k + eps))^q, C = 1, q = 6; normalised    */
+/*    chi_k = gamma_k / sum gamma; stencil k is kept (delta_k = 1) when     */
+/*    chi_k >= C_T, else dropped.                                           */
+/* 5. Adaptive C_T = 10^(-floor(beta_bar)), beta_bar = a1 - a2 (1 - g(m)),   */
+/*    g(m) = (1 - m)^4 (1 + 4 m), m = 1 - min(1, eta / C_r), eta the        */
+/*    smallest of the cell indicators eta_j, j = i-1 .. i+2,                */
+/*    eta_j = (|2 D+ D-| + e) / (D+^2 + D-^2 + e), D+/- = v_{j+/-1} - v_j    */
+/*    (signed), e = 0.9 C_r xi^2 / (1 - 0.9 C_r); a1 = 10.5, a2 = 3.5,      */
+/*    C_r = 0.17, xi = 1e-3.                                                */
+/* 6. omega_k = d_k delta_k / sum d delta with the linear weights           */
+/*    d = (1/20, 9/20, 6/20, 4/20) that make sum d_k p_k the six-point      */
+/*    interpolation; v = sum omega_k p_k.                                   */
+/* parts (may be NULL): beta_0..3, beta_6, tau_6, C_T, delta_0..3, omega_0..3 */
+/* ------------------------------------------------------------------------ */
+#define TENO_C 1.0
+#define TENO_Q 6
+#define TENO_A1 10.5
+#define TENO_A2 3.5
+#define TENO_CR 0.17
+#define TENO_XI 1.0e-3
+
+static double teno_eta(double vm, double v0, double vp)
+{
+    double dp = vp - v0, dm = v0 - vm;
+    double e = 0.9 * TENO_CR / (1.0 - 0.9 * TENO_CR) * TENO_XI * TENO_XI;
+    return (fabs(2.0 * dp * dm) + e) / (dp * dp + dm * dm + e);
+}
+
+double orc_teno6a_parts(const double *v, double eps, double *parts)
+{
+    double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5];
+    /* step 1 */
+    double p[4];
+    p[0] = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+    p[1] = (-b + 5.0 * c + 2.0 * d) / 6.0;
+    p[2] = (2.0 * c + 5.0 * d - e) / 6.0;
+    p[3] = (3.0 * c + 13.0 * d - 5.0 * e + f) / 12.0;
+    /* step 2 */
+    double beta[4];
+    beta[0] = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c)
+            + 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+    beta[1] = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d)
+            + 0.25 * (b - d) * (b - d);
+    beta[2] = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e)
+            + 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+    beta[3] = (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f)
+             + d * (11003.0 * d - 17246.0 * e + 4642.0 * f)
+             + e * (7043.0 * e - 3882.0 * f)
+             + 547.0 * f * f) / 240.0;
+    double beta6 = (a * (271779.0 * a - 2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e
+                         - 245620.0 * f)
+                  + b * (5653317.0 * b - 20427884.0 * c + 17905032.0 * d - 7727988.0 * e + 1325006.0 * f)
+                  + c * (19510972.0 * c - 35817664.0 * d + 15929912.0 * e - 2792660.0 * f)
+                  + d * (17195652.0 * d - 15880404.0 * e + 2863984.0 * f)
+                  + e * (3824847.0 * e - 1429976.0 * f)
+                  + 139633.0 * f * f) / 120960.0;
+    /* step 3 */
+    double tau = fabs(beta6 - (beta[0] + 4.0 * beta[1] + beta[2]) / 6.0);
+    /* step 4 */
+    double gam[4], gsum = 0.0;
+    for (int k = 0; k < 4; k++) {
+        gam[k] = pow(TENO_C + tau / (beta[k] + eps), TENO_Q);
+        gsum += gam[k];
+    }
+    /* step 5 */
+    double eta = teno_eta(a, b, c);
+    double t;
+    t = teno_eta(b, c, d); if (t < eta) eta = t;
+    t = teno_eta(c, d, e); if (t < eta) eta = t;
+    t = teno_eta(d, e, f); if (t < eta) eta = t;
+    double m = 1.0 - fmin(1.0, eta / TENO_CR);
+    double g = pow(1.0 - m, 4) * (1.0 + 4.0 * m);
+    double bbar = TENO_A1 - TENO_A2 * (1.0 - g);
+    double CT = pow(10.0, -floor(bbar));
+    /* step 6 */
+    const double dlin[4] = {1.0 / 20.0, 9.0 / 20.0, 6.0 / 20.0, 4.0 / 20.0};
+    double delta[4], wsum = 0.0, omega[4], val = 0.0;
+    for (int k = 0; k < 4; k++) {
+        delta[k] = gam[k] / gsum < CT ? 0.0 : 1.0;
+        wsum += dlin[k] * delta[k];
+    }
+    for (int k = 0; k < 4; k++) {
+        omega[k] = dlin[k] * delta[k] / wsum;
+        val += omega[k] * p[k];
+    }
+    if (parts) {
+        for (int k = 0; k < 4; k++) parts[k] = beta[k];
+        parts[4] = beta6;
+        parts[5] = tau;
+        parts[6] = CT;
+        for (int k = 0; k < 4; k++) parts[7 + k] = delta[k];
+        for (int k = 0; k < 4; k++) parts[11 + k] = omega[k];
+    }
+    return val;
+}
+
+double orc_teno6a(const double *v, double eps) { return orc_teno6a_parts(v, eps, NULL); }
+
+/* one-sided value of the configured scheme from the six-cell stencil v[0..5] =
+ * v_{i-2..i+3} (the mirrored stencil gives the other side) */
+static double recon_one(const orc_cfg *c, double v0, double v1, double v2, double v3, double v4, double v5)
+{
+    if (c->scheme == 1) {
+        double v[6] = {v0, v1, v2, v3, v4, v5};
+        return orc_teno6a(v, c->weno_eps);
+    }
+    return orc_weno5z(v0, v1, v2, v3, v4, c->weno_eps);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -594,16 +724,16 @@ static void invert(int n, double A[MAXC][MAXC], double Inv[MAXC][MAXC])
 }
 
 /* Face states W^-/+ at the face between cells i and i+1 (direction d) from the
- * six-cell stencil v[s] = W_{i-2+s}: WENO5-Z of each primitive component
- * (recon 0), or of each characteristic component of the frozen face state
- * W_{i+1/2} = (W_i + W_{i+1})/2 (recon 1). */
+ * six-cell stencil v[s] = W_{i-2+s}: WENO5-Z or TENO6-A (scheme) of each
+ * primitive component (recon 0), or of each characteristic component of the
+ * frozen face state W_{i+1/2} = (W_i + W_{i+1})/2 (recon 1). */
 static void reconstruct(const orc_cfg *c, int d, double v[6][MAXC], double *WL, double *WR)
 {
     int nc = orc_ncomp(c);
     if (c->recon != 1) {
         for (int m = 0; m < nc; m++) {
-            WL[m] = orc_weno5z(v[0][m], v[1][m], v[2][m], v[3][m], v[4][m], c->weno_eps);
-            WR[m] = orc_weno5z(v[5][m], v[4][m], v[3][m], v[2][m], v[1][m], c->weno_eps);
+            WL[m] = recon_one(c, v[0][m], v[1][m], v[2][m], v[3][m], v[4][m], v[5][m]);
+            WR[m] = recon_one(c, v[5][m], v[4][m], v[3][m], v[2][m], v[1][m], v[0][m]);
         }
         return;
     }
@@ -618,8 +748,8 @@ static void reconstruct(const orc_cfg *c, int d, double v[6][MAXC], double *WL, 
             ch[s][q] = acc;
         }
     for (int q = 0; q < nc; q++) {
-        cl[q] = orc_weno5z(ch[0][q], ch[1][q], ch[2][q], ch[3][q], ch[4][q], c->weno_eps);
-        cr[q] = orc_weno5z(ch[5][q], ch[4][q], ch[3][q], ch[2][q], ch[1][q], c->weno_eps);
+        cl[q] = recon_one(c, ch[0][q], ch[1][q], ch[2][q], ch[3][q], ch[4][q], ch[5][q]);
+        cr[q] = recon_one(c, ch[5][q], ch[4][q], ch[3][q], ch[2][q], ch[1][q], ch[0][q]);
     }
     for (int m = 0; m < nc; m++) {
         double a = 0.0, b = 0.0;
@@ -652,7 +782,7 @@ static void face_flux(const orc_cfg *c, const padded *p, int d, int i, int j, in
     int nc = orc_ncomp(c);
     const int *o = DI[d];
     double WL[MAXC], WR[MAXC];
-    /* step 3: WENO5-Z reconstruction, both sides */
+    /* step 3: WENO5-Z / TENO6-A reconstruction, both sides */
     double v[6][MAXC];
     for (int s = 0; s < 6; s++)
         get_w(p, i + (s - 2) * o[0], j + (s - 2) * o[1], k + (s - 2) * o[2], v[s]);
