@@ -46,6 +46,7 @@ class _Cfg(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("visc_law", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
+        ("visc_order", ctypes.c_int32), ("pad3_", ctypes.c_int32),
     ]
 
 
@@ -74,6 +75,7 @@ class Config:
     recon: int = 0                # 0: primitive variables, 1: characteristic variables
     visc_law: int = 0             # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
     scheme: int = 0               # 0: WENO5-Z, 1: TENO6-A (Sec. 3.2 step 3)
+    visc_order: int = 4           # central viscous stencils: 4th or 6th order
     T_ref: float = 1.0
     sutherland: float = 0.0
     gas_R: float = 1.0
@@ -104,6 +106,7 @@ class Config:
         c.recon = self.recon
         c.visc_law = self.visc_law
         c.scheme = self.scheme
+        c.visc_order = self.visc_order
         c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
         return c
 

@@ -25,8 +25,8 @@
  *  - Einfeldt speeds use Roe averages for u-bar and c-bar;
  *  - sgn(0) = 0 in the HLLC flux;
  *  - conductivity lambda = mu c_p / Pr (the printed ratio is inverted);
- *  - 4th-order central viscous stencils (normal derivative at the face,
- *    tangential derivative at cell centres then interpolated);
+ *  - 4th- or 6th-order central viscous stencils (normal derivative at the
+ *    face, tangential derivative at cell centres then interpolated);
  *  - the flux limiter's pseudo-time state is the split forward-Euler state
  *    U_i -/+ 2 D (dt/dx) (F_face - F(U_i));
  *  - CFL: dt = CFL * min(min_d dx_d/(|u_d|+c), (3/14) rho dx_min^2 / mu);
@@ -71,6 +71,8 @@ typedef struct {
     double T_ref;        /* reference temperature of the viscosity law */
     double sutherland;   /* Sutherland's constant C */
     double gas_R;        /* specific gas constant, T = p / (rho R) */
+    int32_t visc_order;  /* order of the central viscous stencils: 4 (0 selects 4) or 6 */
+    int32_t pad3_;
 } orc_cfg;
 
 #define NH 3   /* halo width: WENO5 at face i-1/2 reads cells i-3 .. i+2 */
@@ -582,16 +584,20 @@ static double viscosity(const orc_cfg *c, double T)
     return c->mu;
 }
 
-/* 4th-order central derivative of q at a cell centre in direction e:
- * (q_{-2} - 8 q_{-1} + 8 q_{+1} - q_{+2}) / (12 h), grouped so that a constant gives 0 */
+/* central derivative of q at a cell centre in direction e, 4th order:
+ * (q_{-2} - 8 q_{-1} + 8 q_{+1} - q_{+2}) / (12 h), 6th order:
+ * (-q_{-3} + 9 q_{-2} - 45 q_{-1} + 45 q_{+1} - 9 q_{+2} + q_{+3}) / (60 h);
+ * grouped so that a constant gives 0 */
 static double dcell(const orc_cfg *c, const padded *p, int m, int i, int j, int k, int e, double h)
 {
     const int *o = DI[e];
-    double qm2 = visc_q(c, p, m, i - 2 * o[0], j - 2 * o[1], k - 2 * o[2]);
-    double qm1 = visc_q(c, p, m, i - o[0], j - o[1], k - o[2]);
-    double qp1 = visc_q(c, p, m, i + o[0], j + o[1], k + o[2]);
-    double qp2 = visc_q(c, p, m, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2]);
-    return ((qm2 - qp2) + 8.0 * (qp1 - qm1)) / (12.0 * h);
+    double q[7];
+    int r = c->visc_order == 6 ? 3 : 2;
+    for (int s = -r; s <= r; s++)
+        if (s != 0) q[s + 3] = visc_q(c, p, m, i + s * o[0], j + s * o[1], k + s * o[2]);
+    if (r == 3)
+        return (45.0 * (q[4] - q[2]) - 9.0 * (q[5] - q[1]) + (q[6] - q[0])) / (60.0 * h);
+    return ((q[1] - q[5]) + 8.0 * (q[4] - q[2])) / (12.0 * h);
 }
 
 /* 4th-order interpolation to the face from cells a,b | c,d: (-a + 9b + 9c - d)/16 */
@@ -600,31 +606,49 @@ static double interp4(double a, double b, double cc, double d)
     return (9.0 * (b + cc) - (a + d)) / 16.0;
 }
 
+/* 6th-order interpolation to the face from cells q[0..2] | q[3..5]:
+ * (3 q0 - 25 q1 + 150 q2 + 150 q3 - 25 q4 + 3 q5) / 256 */
+static double interp6(const double *q)
+{
+    return (150.0 * (q[2] + q[3]) - 25.0 * (q[1] + q[4]) + 3.0 * (q[0] + q[5])) / 256.0;
+}
+
+/* Viscous face flux (Sec. 2.1 dissipative fluxes) at the face between cell
+ * (i,j,k) and its +d neighbour with central stencils of order 4 (cells -1..+2
+ * across the face) or 6 (cells -2..+3): face values and the normal derivative
+ * from the cells across the face, tangential derivatives at those cells'
+ * centres, then interpolated to the face. */
 static void viscous_flux(const orc_cfg *c, const padded *p, int d, int i, int j, int k, double *Fd)
 {
     const int *o = DI[d];
     double h[3] = {c->dx, c->dy, c->dz};
-    /* the four cells across the face: offsets -1, 0, +1, +2 along d */
-    int ci[4], cj[4], ck[4];
-    for (int s = 0; s < 4; s++) {
-        ci[s] = i + (s - 1) * o[0];
-        cj[s] = j + (s - 1) * o[1];
-        ck[s] = k + (s - 1) * o[2];
+    int six = c->visc_order == 6;
+    int ns = six ? 6 : 4, first = six ? -2 : -1;
+    int ci[6], cj[6], ck[6];
+    for (int s = 0; s < ns; s++) {
+        ci[s] = i + (s + first) * o[0];
+        cj[s] = j + (s + first) * o[1];
+        ck[s] = k + (s + first) * o[2];
     }
     /* gradient g[m][e] = d q_m / d x_e at the face, m = u,v,w,T; face values qf */
     double g[4][3], qf[4];
     for (int m = 0; m < 4; m++) {
-        double q[4];
-        for (int s = 0; s < 4; s++) q[s] = visc_q(c, p, m, ci[s], cj[s], ck[s]);
-        qf[m] = interp4(q[0], q[1], q[2], q[3]);
+        double q[6];
+        for (int s = 0; s < ns; s++) q[s] = visc_q(c, p, m, ci[s], cj[s], ck[s]);
+        qf[m] = six ? interp6(q) : interp4(q[0], q[1], q[2], q[3]);
         for (int e = 0; e < 3; e++) {
             if (e == d) {
-                /* normal: (q_{i-1} - 27 q_i + 27 q_{i+1} - q_{i+2}) / (24 h) */
-                g[m][e] = ((q[0] - q[3]) + 27.0 * (q[2] - q[1])) / (24.0 * h[d]);
+                if (six)
+                    /* (2250 (q_{+1} - q_0) - 125 (q_{+2} - q_{-1}) + 9 (q_{+3} - q_{-2})) / (1920 h) */
+                    g[m][e] = (2250.0 * (q[3] - q[2]) - 125.0 * (q[4] - q[1]) + 9.0 * (q[5] - q[0]))
+                            / (1920.0 * h[d]);
+                else
+                    /* (q_{i-1} - 27 q_i + 27 q_{i+1} - q_{i+2}) / (24 h) */
+                    g[m][e] = ((q[0] - q[3]) + 27.0 * (q[2] - q[1])) / (24.0 * h[d]);
             } else {
-                double t[4];
-                for (int s = 0; s < 4; s++) t[s] = dcell(c, p, m, ci[s], cj[s], ck[s], e, h[e]);
-                g[m][e] = interp4(t[0], t[1], t[2], t[3]);
+                double t[6];
+                for (int s = 0; s < ns; s++) t[s] = dcell(c, p, m, ci[s], cj[s], ck[s], e, h[e]);
+                g[m][e] = six ? interp6(t) : interp4(t[0], t[1], t[2], t[3]);
             }
         }
     }

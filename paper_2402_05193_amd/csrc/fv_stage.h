@@ -1,0 +1,885 @@
+// fv_stage.h -- the fused finite-volume RHS / TVD-RK3 stage kernel for gfx950.
+// Instantiated per precision and model by fv_stage_inst.hip (the kernels of a
+// variant family) and fv_stage_launch.hip (dispatch and the batched kernels),
+// so that the instantiations compile in parallel.
+//
+// One kernel evaluates R_NSE (arXiv:2402.05193 Eq. (FVD), plus the volume
+// fraction source of Sec. 3.6) for a block of cells and applies one Shu-Osher
+// stage (Sec. 3.4) -- or writes R itself.  Face states and fluxes never
+// leave the chip.
+//
+// Work decomposition ("2.5-D z-march"):
+//  * a workgroup owns a BX x BY column tile and a chunk of z-planes and marches
+//    through them plane by plane;
+//  * each thread owns one (x, y) column and keeps a 6-plane register window of
+//    primitive states W(s-3..s+2) of that column: the z-direction
+//    reconstruction, Riemann solve and viscous flux run entirely in registers;
+//  * the current plane s, with a 3-cell ring of x/y halo cells mapped through
+//    the boundary conditions, is staged in LDS as primitives; x- and y-face
+//    work runs as flat task lists over LDS (cell reconstructions write both
+//    face states of a cell, sharing the smoothness indicators; face tasks
+//    solve the Riemann problem in place);
+//  * z-faces complete one plane behind, so cell s-2 is finalised at step s
+//    (combined with U^n and written once, coalesced, x fastest).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fv_kernels.h"
+#include "fv_physics.h"
+
+namespace fv {
+
+template <typename Real>
+__device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* __restrict__ U, int gi, int gj,
+                                          int gk, Real* u, int nc, int V, bool interior_xy)
+{
+    bool fx = false, fy = false, fz = false;
+    int i = gi, j = gj;
+    if (!interior_xy) {
+        i = map_index(gi, a.nx, a.bc[0], a.bc[1], fx);
+        j = map_index(gj, a.ny, a.bc[2], a.bc[3], fy);
+    }
+    const int k = map_index(gk, a.nz, a.bc[4], a.bc[5], fz);
+    const long long q = ((long long)k * a.ny + j) * a.nx + i;
+    for (int m = 0; m < nc; m++) u[m] = U[m * a.ncell + q];
+    if (fx) u[V] = -u[V];
+    if (fy) u[V + 1] = -u[V + 1];
+    if (fz) u[V + 2] = -u[V + 2];
+}
+
+// Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3)
+// from the preloaded U^(k) (uk) and U^n (un) of the cell; the written values
+// are returned in `out` for the optional CFL reduction.
+template <typename Real, int NC>
+__device__ __forceinline__ void store_cell_impl(const StageArgs<Real>& a, long long q, const Real* r, Real dt,
+                                                const Real* uk, const Real* un, Real* out)
+{
+    if (a.mode == 0) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) out[m] = r[m];
+    } else if (a.mode == 1) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) out[m] = uk[m] + dt * r[m];
+    } else if (a.mode == 2) {
+        const Real c1 = Real(0.75), c2 = Real(0.25);
+#pragma unroll
+        for (int m = 0; m < NC; m++) out[m] = c1 * un[m] + c2 * uk[m] + (c2 * dt) * r[m];
+    } else {
+        const Real c1 = Real(1.0 / 3.0), c2 = Real(2.0 / 3.0);
+#pragma unroll
+        for (int m = 0; m < NC; m++) out[m] = c1 * un[m] + c2 * uk[m] + (c2 * dt) * r[m];
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) a.out[m * a.ncell + q] = out[m];
+}
+
+// Inverse CFL time step of a conservative state: max(max_d (|u_d| + c)/dx_d, kvisc/rho).
+template <typename Real, int MODEL, bool VLAW>
+__device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Real* u)
+{
+    constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V;
+    Real w[NC];
+    cons_to_prim<Real, MODEL>(a.mat, u, w);
+    const Real ir = rcp(density<Real, MODEL>(w));
+    const Real c = sqrt_fast(rhoc2<Real, MODEL>(a.mat, w) * ir);
+    Real v = fmax((fabs(w[V]) + c) * a.idx, fmax((fabs(w[V + 1]) + c) * a.idy, (fabs(w[V + 2]) + c) * a.idz));
+    if constexpr (MODEL == NS) {
+        Real kv = Real(a.kvisc);
+        if constexpr (VLAW) kv = visc_mu(a.vl, w[Layout<MODEL>::P] * ir) * Real(a.kvisc_h);
+        v = fmax(v, kv * ir);
+    }
+    const double d = (double)v;
+    return d >= 0.0 ? d : __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
+}
+
+// LDS geometry of one tile of BX x BY cells worked on by NTH threads
+// (NTH >= BX * BY; the x/y task lists are sized to fit NTH in one round)
+template <typename Real, int MODEL, int BX, int BY, int NTH>
+struct Tile {
+    static constexpr int NC = Layout<MODEL>::NC;
+    static constexpr bool VISC = MODEL == NS;
+    static constexpr int NT = NTH;
+    static constexpr int NCELL = BX * BY;
+    static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho) of the LDS plane
+    static constexpr int PX = BX + 6, PY = BY + 6;  // plane with 3-cell halo
+    static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
+    static constexpr int NFMAX = NFX > NFY ? NFX : NFY;
+    static constexpr int WP_SIZE = NW * PY * PX;
+    static constexpr int FB_SIZE = 2 * NC * NFMAX;       // face states (left, right), fluxes in place
+    static constexpr int UH_SIZE = MODEL == DIM ? NFMAX : 0;
+    static constexpr int RX = (BX + 4) * BY, RY = BX * (BY + 4);  // viscous cell regions
+    static constexpr int DZ_SIZE = VISC ? 2 * RX + 2 * RY : 0;    // d/dz of (u,w) on RX, (v,w) on RY
+    static constexpr int DT_SIZE = VISC ? 2 * (RX > RY ? RX : RY) : 0;  // in-plane tangential d/dx_t
+    static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : 0);
+    // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
+    // five-equation model keeps them in registers instead (LDS budget)
+    static constexpr bool ACC_LDS = MODEL != DIM;
+    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : 0;
+    static constexpr size_t bytes()
+    {
+        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE);
+    }
+};
+
+// One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
+template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+__device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
+{
+    using L = Layout<MODEL>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH>;
+    constexpr int NC = L::NC, V = L::V, P = L::P;
+    constexpr bool VISC = TL::VISC;
+    constexpr bool ACC_LDS = TL::ACC_LDS;
+    constexpr int PX = TL::PX, PY = TL::PY;
+    constexpr int NT = NTH;
+    constexpr int NCELL = BX * BY;
+    constexpr int PLANE = PY * PX;
+    static_assert(NT >= NCELL && NT % 64 == 0, "threads must cover the tile");
+
+    Real* Wp = reinterpret_cast<Real*>(smem_raw);
+    Real* FB = Wp + TL::WP_SIZE;
+    Real* UHB = FB + TL::FB_SIZE;
+    Real* DZX = UHB + TL::UH_SIZE;  // [2][BY][BX+4]   (u, w) d/dz, x-face region
+    Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
+    Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
+    Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NCELL]  x/y partial sums of R
+
+    const Material<Real> mat = a.mat;
+    const Tolerances<Real> tol = a.tol;
+    const Real weps = a.weno_eps;
+    const Real dt = a.dt_dev ? Real(*a.dt_dev) : Real(a.dt);
+
+    const int tid = threadIdx.x;
+    const bool has_cell = tid < NCELL;  // threads beyond the tile only take x/y tasks
+    const int tx = tid % BX, ty = has_cell ? tid / BX : 0;
+    // task lists have a few tasks more than threads; the wave that takes the
+    // remainder rotates with the workgroup so co-resident groups spread it over SIMDs
+    const int rt = FV_ROTATE_TASKS ? (tid + 64 * (bid & 3)) % NT : tid;
+    int b = bid;
+    // blocks of one tile column are consecutive; consecutive tiles share an XCD's L2
+    const int chunk = b % a.nchunks;
+    b /= a.nchunks;
+    const int tileX = b % a.tiles_x;
+    const int tileY = b / a.tiles_x;
+    const int x0 = tileX * BX, y0 = tileY * BY;
+    const int z0 = chunk * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own_valid = has_cell && gx < a.nx && gy < a.ny;
+    // the tile and its 3-cell x/y halo lie inside the domain: no boundary mapping in x, y
+    const bool interior_xy = x0 >= 3 && x0 + BX + 3 <= a.nx && y0 >= 3 && y0 + BY + 3 <= a.ny;
+
+    auto wp = [&](int f, int i, int j) -> Real& { return Wp[f * PLANE + (j + 3) * PX + (i + 3)]; };
+
+    // primitive state of an arbitrary (possibly outside) cell
+    auto load_w = [&](int gi, int gj, int gk, Real* w) {
+        Real u[NC];
+        load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V, interior_xy);
+        cons_to_prim<Real, MODEL>(mat, u, w);
+    };
+    auto stage_w = [&](int i, int j, const Real* w) {
+#pragma unroll
+        for (int f = 0; f < NC; f++) wp(f, i, j) = w[f];
+        if constexpr (VISC) wp(NC, i, j) = w[P] * rcp(w[0]);  // T = p / rho
+    };
+
+    // reconstruction variant: WENO5-Z of primitive variables per cell (both faces of a
+    // cell share the smoothness indicators), or per face (characteristic variables,
+    // TENO6-A): then a z face reads six planes and the window holds seven
+    constexpr bool FACE = REC != REC_WENO_PRIM;
+    constexpr bool CHARV = REC == REC_WENO_CHAR || REC == REC_TENO_CHAR;
+    constexpr bool TENO = REC == REC_TENO_PRIM || REC == REC_TENO_CHAR;
+    // register window W(s-3 .. s+2) of the own column
+    constexpr int NWIN = FACE ? 7 : 6, WO = FACE ? 1 : 0;  // face tasks need s-4 .. s+2
+    Real win[NWIN][NC];
+    const int s_begin = VISC ? z0 - 2 : z0;
+#pragma unroll
+    for (int q = 0; q < NWIN - 1; q++) {
+        if (has_cell) load_w(gx, gy, s_begin - 3 - WO + q, win[q]);
+        else
+#pragma unroll
+            for (int f = 0; f < NC; f++) win[q][f] = Real(1);
+    }
+
+    Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
+    Real accA[NC], accB[NC];  // x/y part of R of cells s-2, s-1 (register variant)
+    Real srcA = 0, srcB = 0;  // DIM: x/y part of sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
+    Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
+    Real uhzl = 0;            // its upwinded normal velocity (DIM)
+    Real Dc[3][4];            // NS: (dw/dx, du/dx, dw/dy, dv/dy) at planes s-3, s-2, s-1
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        vminus[m] = 0;
+        accA[m] = 0;
+        accB[m] = 0;
+        Fzl[m] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) Dc[q][c] = 0;
+
+    double tmax = 0.0;  // CFL reduction over the finalised cells (stage 3)
+    const Real idx = a.idx, idy = a.idy, idz = a.idz;
+    const Real lamx = Real(2 * a.ndim) * dt * idx;
+    const Real lamy = Real(2 * a.ndim) * dt * idy;
+    const Real lamz = Real(2 * a.ndim) * dt * idz;
+
+    for (int s = s_begin; s <= z1 + 1; s++) {
+        // own column, plane s+2: issued now, converted after the barrier below
+        Real raw[NC];
+        if (has_cell) load_cell<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, V, interior_xy);
+        else
+#pragma unroll
+            for (int f = 0; f < NC; f++) raw[f] = Real(1);
+        if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+        const bool xy = (s >= z0) && (s < z1);
+        const bool need_plane = xy || (VISC && s >= z0 - 2);
+        Real accC[NC];
+        Real srcC = 0;
+        Real Dnew[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < NC; m++) accC[m] = 0;
+
+        // U^(k), U^n of the cell finalised in this step (s-2), loaded early
+        Real pre_k[NC], pre_n[NC];
+        const bool fin = s >= z0 + 2 && own_valid;
+        if (FV_PREFETCH_RK && fin && a.mode != 0) {
+            const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                pre_k[m] = a.Uk[m * a.ncell + q];
+                pre_n[m] = a.mode >= 2 ? a.Un[m * a.ncell + q] : Real(0);
+            }
+        }
+
+        if (need_plane) {
+            // halo cell of this thread (at most one: NHALO <= NT), loaded before the barrier
+            static_assert(TL::NHALO <= NT, "one halo cell per thread");
+            int hi = 0, hj = 0;
+            Real hu[NC];
+            const bool has_halo = tid < TL::NHALO;
+            if (has_halo) {
+                const int h = tid;
+                if (h < 6 * BY) {
+                    hj = h / 6;
+                    const int k = h % 6;
+                    hi = k < 3 ? k - 3 : BX + k - 3;
+                } else if (h < 6 * BY + 6 * BX) {
+                    const int hh = h - 6 * BY;
+                    hi = hh % BX;
+                    const int k = hh / BX;
+                    hj = k < 3 ? k - 3 : BY + k - 3;
+                } else {
+                    const int hh = h - 6 * BY - 6 * BX;  // 2-deep corners (viscous cross terms)
+                    const int ci = hh & 3, cj = hh >> 2;
+                    hi = ci < 2 ? ci - 2 : BX + ci - 2;
+                    hj = cj < 2 ? cj - 2 : BY + cj - 2;
+                }
+                if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+            }
+            // the plane buffer is overwritten below: after a step with x/y phases their
+            // barriers already ordered every read of it; after a warm-up step (only the
+            // in-plane derivatives read it) a barrier is needed here
+            const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
+            if (!FV_SKIP_PLANE_BARRIER || !prev_xy) __syncthreads();
+            if (!FV_EARLY_HALO && has_halo) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+            if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+            // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
+            if (has_cell) stage_w(tx, ty, win[3 + WO]);
+            if (has_halo) {
+                Real w[NC];
+                cons_to_prim<Real, MODEL>(mat, hu, w);
+                stage_w(hi, hj, w);
+            }
+            if constexpr (VISC) {
+                if (xy) {
+                    // d/dz of the velocity at plane s: own column from the window
+                    const Real i12 = a.inv12dz;
+                    if (has_cell) {
+                        Real dz[3];
+#pragma unroll
+                        for (int c = 0; c < 3; c++)
+                            dz[c] = dcell(win[1 + WO][V + c], win[2 + WO][V + c], win[4 + WO][V + c], win[5 + WO][V + c], i12);
+                        DZX[0 * TL::RX + ty * (BX + 4) + tx + 2] = dz[0];
+                        DZX[1 * TL::RX + ty * (BX + 4) + tx + 2] = dz[2];
+                        DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
+                        DZY[1 * TL::RY + (ty + 2) * BX + tx] = dz[2];
+                    }
+                    // halo columns of the viscous regions: from memory, taken by the
+                    // highest-numbered threads (the regular halo ring uses the lowest)
+                    for (int h = NT - 1 - tid; h < 4 * BY + 4 * BX && h >= 0; h += NT) {
+                        int i, j;
+                        if (h < 4 * BY) {
+                            j = h / 4;
+                            const int k = h % 4;
+                            i = k < 2 ? k - 2 : BX + k - 2;
+                        } else {
+                            const int hh = h - 4 * BY;
+                            i = hh % BX;
+                            const int k = hh / BX;
+                            j = k < 2 ? k - 2 : BY + k - 2;
+                        }
+                        // velocities of planes s-2, s-1, s+1, s+2 (density and momenta only)
+                        Real vel[4][3];
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const int dk = k < 2 ? k - 2 : k - 1;
+                            bool fx = false, fy = false, fz = false;
+                            const int ii = interior_xy ? x0 + i : map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
+                            const int jj = interior_xy ? y0 + j : map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
+                            const int kk = map_index(s + dk, a.nz, a.bc[4], a.bc[5], fz);
+                            const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
+                            const Real ir = rcp(a.Uk[qq]);
+                            vel[k][0] = (fx ? -a.Uk[V * a.ncell + qq] : a.Uk[V * a.ncell + qq]) * ir;
+                            vel[k][1] = (fy ? -a.Uk[(V + 1) * a.ncell + qq] : a.Uk[(V + 1) * a.ncell + qq]) * ir;
+                            vel[k][2] = (fz ? -a.Uk[(V + 2) * a.ncell + qq] : a.Uk[(V + 2) * a.ncell + qq]) * ir;
+                        }
+                        Real d[3];
+#pragma unroll
+                        for (int c = 0; c < 3; c++) d[c] = dcell(vel[0][c], vel[1][c], vel[2][c], vel[3][c], i12);
+                        if (h < 4 * BY) {
+                            DZX[0 * TL::RX + j * (BX + 4) + i + 2] = d[0];
+                            DZX[1 * TL::RX + j * (BX + 4) + i + 2] = d[2];
+                        } else {
+                            DZY[0 * TL::RY + (j + 2) * BX + i] = d[1];
+                            DZY[1 * TL::RY + (j + 2) * BX + i] = d[2];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (VISC && has_cell) {
+                // in-plane derivatives of the own column for the z faces
+                const Real i12x = a.inv12dx, i12y = a.inv12dy;
+                Dnew[0] = dcell(wp(V + 2, tx - 2, ty), wp(V + 2, tx - 1, ty), wp(V + 2, tx + 1, ty), wp(V + 2, tx + 2, ty), i12x);
+                Dnew[1] = dcell(wp(V, tx - 2, ty), wp(V, tx - 1, ty), wp(V, tx + 1, ty), wp(V, tx + 2, ty), i12x);
+                Dnew[2] = dcell(wp(V + 2, tx, ty - 2), wp(V + 2, tx, ty - 1), wp(V + 2, tx, ty + 1), wp(V + 2, tx, ty + 2), i12y);
+                Dnew[3] = dcell(wp(V + 1, tx, ty - 2), wp(V + 1, tx, ty - 1), wp(V + 1, tx, ty + 1), wp(V + 1, tx, ty + 2), i12y);
+            }
+        }
+
+        if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+
+        // ---- z work of the own column (registers only): finalises cell s-2
+        if (has_cell && s >= z0) {
+            // primitive variables: the reconstruction of cell s-1 from W(s-3 .. s+1) gives
+            // its face values at s-3/2 (used now) and s-1/2 (carried to the next step)
+            Real vm_new[NC], vp[NC];
+            if constexpr (!FACE) {
+#pragma unroll
+                for (int m = 0; m < NC; m++)
+                    weno5z_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], weps, vm_new[m], vp[m]);
+            }
+            if (s >= z0 + 1) {
+                // z face s-3/2 between cells s-2 (win[1]) and s-1 (win[2])
+                Real Fd[4];
+                if constexpr (VISC) {
+                    // viscous part first: its inputs are the window and the carried derivatives
+                    const Real i24 = a.inv24dz;
+                    Real dn[4], vf[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const Real q0 = win[WO][V + c], q1 = win[1 + WO][V + c], q2 = win[2 + WO][V + c], q3 = win[3 + WO][V + c];
+                        dn[c] = dface(q0, q1, q2, q3, i24);
+                        vf[c] = ifc(q0, q1, q2, q3);
+                    }
+                    const Real th0 = win[WO][P] * rcp(win[WO][0]), th1 = win[1 + WO][P] * rcp(win[1 + WO][0]);
+                    const Real th2 = win[2 + WO][P] * rcp(win[2 + WO][0]), th3 = win[3 + WO][P] * rcp(win[3 + WO][0]);
+                    dn[3] = dface(th0, th1, th2, th3, i24);
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        muf = visc_mu(a.vl, ifc(th0, th1, th2, th3));
+                        kf = muf * a.vl.kfac;
+                    }
+                    const Real g_xw = ifc(Dc[0][0], Dc[1][0], Dc[2][0], Dnew[0]);  // dw/dx
+                    const Real g_yw = ifc(Dc[0][2], Dc[1][2], Dc[2][2], Dnew[2]);  // dw/dy
+                    const Real g_xu = ifc(Dc[0][1], Dc[1][1], Dc[2][1], Dnew[1]);  // du/dx
+                    const Real g_yv = ifc(Dc[0][3], Dc[1][3], Dc[2][3], Dnew[3]);  // dv/dy
+                    viscous_flux_from_gradients<Real, 2>(dn, vf, g_xw, g_yw, g_xu, g_yv, muf, kf, Fd);
+                    __builtin_amdgcn_sched_barrier(0);  // keep the two flux parts from interleaving (registers)
+                }
+                Real wl[NC], wr[NC], F[NC], uh;
+                if constexpr (CHARV) {
+                    // characteristic variables of the face's frozen state, stencil s-4 .. s+1
+                    char_face_states<Real, MODEL, 2, TENO>(mat, [&](int q, int m) { return win[q][m]; }, weps, wl, wr);
+                } else if constexpr (TENO) {
+#pragma unroll
+                    for (int m = 0; m < NC; m++)
+                        teno6a_pair(win[0][m], win[1][m], win[2][m], win[3][m], win[4][m], win[5][m], weps, wl[m], wr[m]);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wl[m] = vminus[m];
+                        wr[m] = vp[m];
+                    }
+                }
+                if constexpr (POS) {
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = win[1 + WO][m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = win[2 + WO][m];
+                    hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1 + WO], win[2 + WO], F, uh, lamz))
+                        hllc<Real, MODEL, 2>(mat, win[1 + WO], win[2 + WO], F, uh);
+                } else {
+                    hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+                if (s >= z0 + 2 && own_valid) {
+                    // finalise cell s-2: R = (x/y part) - (F_{s-3/2} - F_{s-5/2}) / dz
+                    const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
+                    Real r[NC];
+                    if constexpr (ACC_LDS) {
+                        const Real* slot = ACC + (s & 1) * NC * NCELL + tid;
+#pragma unroll
+                        for (int m = 0; m < NC; m++) r[m] = slot[m * NCELL] - (F[m] - Fzl[m]) * idz;
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
+                    }
+                    if constexpr (MODEL == DIM) r[6] += win[1 + WO][6] * (srcA + (uh - uhzl) * idz);
+                    Real unew[NC];
+                    if (!FV_PREFETCH_RK && a.mode != 0) {
+#pragma unroll
+                        for (int m = 0; m < NC; m++) {
+                            pre_k[m] = a.Uk[m * a.ncell + q];
+                            pre_n[m] = a.mode >= 2 ? a.Un[m * a.ncell + q] : Real(0);
+                        }
+                    }
+                    store_cell_impl<Real, NC>(a, q, r, dt, pre_k, pre_n, unew);
+                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, VLAW>(a, unew));
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) Fzl[m] = F[m];
+                uhzl = uh;
+            }
+            if constexpr (!FACE) {
+#pragma unroll
+                for (int m = 0; m < NC; m++) vminus[m] = vm_new[m];
+            }
+        }
+
+        if (xy) {
+            Real* slot = ACC + (s & 1) * NC * NCELL + tid;  // partial sums of cell s (ACC_LDS)
+            // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
+            Real* FL = FB;
+            Real* FR = FB + NC * TL::NFX;
+            if constexpr (CHARV) {
+                // one task per x face: characteristic reconstruction of both face states
+                for (int t = rt; t < TL::NFX; t += NT) {
+                    const int j = t / (BX + 1), f = t - j * (BX + 1);
+                    Real wl[NC], wr[NC];
+                    char_face_states<Real, MODEL, 0, TENO>(mat, [&](int q, int m) { return wp(m, f - 3 + q, j); }, weps,
+                                                           wl, wr);
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        FL[m * TL::NFX + t] = wl[m];
+                        FR[m * TL::NFX + t] = wr[m];
+                    }
+                }
+            } else if constexpr (TENO) {
+                // one item = one component of one x face (faces between cells f-1 and f)
+                for (int it = rt; it < NC * TL::NFX; it += NT) {
+                    const int m = it / TL::NFX, t = it - m * TL::NFX;
+                    const int j = t / (BX + 1), f = t - j * (BX + 1);
+                    const Real* c = &wp(m, f - 3, j);
+                    teno6a_pair(c[0], c[1], c[2], c[3], c[4], c[5], weps, FL[it], FR[it]);
+                }
+            } else if constexpr (FV_RECON_ITEMS) {
+                // one item = one component of one cell; consecutive lanes take consecutive cells
+                constexpr int NTX = (BX + 2) * BY;
+                auto item = [&](int it) {
+                    const int m = it / NTX, t = it - m * NTX;
+                    const int j = t / (BX + 2), i = t - j * (BX + 2) - 1;
+                    const Real* c = &wp(m, i, j);
+                    Real vm, vp;
+                    weno5z_pair(c[-2], c[-1], c[0], c[1], c[2], weps, vm, vp);
+                    if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
+                    if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                };
+#pragma unroll FV_RECON_UNROLL
+                for (int it = rt; it < NC * NTX; it += NT) item(it);
+            } else {
+                for (int t = rt; t < (BX + 2) * BY; t += NT) {
+                    const int j = t / (BX + 2), i = t % (BX + 2) - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
+                                    weps, vm, vp);
+                        if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
+                        if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
+                    }
+                }
+            }
+            if constexpr (VISC) {
+                // d/dy of u (c = 0) and v (c = 1) on the x-face region
+                const Real i12 = a.inv12dy;
+                for (int it = rt; it < 2 * TL::RX; it += NT) {
+                    const int c = it >= TL::RX, t = it - c * TL::RX;
+                    const int j = t / (BX + 4), i = t % (BX + 4) - 2;
+                    DT[it] = dcell(wp(V + c, i, j - 2), wp(V + c, i, j - 1), wp(V + c, i, j + 1), wp(V + c, i, j + 2), i12);
+                }
+            }
+            __syncthreads();
+            // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
+            for (int t = rt; t < TL::NFX; t += NT) {
+                const int j = t / (BX + 1), f = t % (BX + 1);
+                Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    wl[m] = FL[m * TL::NFX + t];
+                    wr[m] = FR[m * TL::NFX + t];
+                }
+                if constexpr (POS) {
+                    Real wi[NC], wj[NC];
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wi[m] = wp(m, f - 1, j);
+                        wj[m] = wp(m, f, j);
+                    }
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                    hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx))
+                        hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
+                } else {
+                    hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    const int r0 = j * (BX + 4) + f;  // region index of cell f-2
+                    Real Fd[4];
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        const Real* th = &wp(NC, f - 2, j);
+                        muf = visc_mu(a.vl, ifc(th[0], th[1], th[2], th[3]));
+                        kf = muf * a.vl.kfac;
+                    }
+                    viscous_flux_lds<Real, 0>(&wp(V, f - 2, j), &wp(NC, f - 2, j), 1, PLANE, DT + r0, DZX + r0,
+                                              DT + TL::RX + r0, DZX + TL::RX + r0, 1, muf, kf, a.inv24dx, Fd);
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) FL[m * TL::NFX + t] = F[m];
+                if constexpr (MODEL == DIM) UHB[t] = uh;
+            }
+            __syncthreads();
+            // ---- P3: x divergence of the own cell
+            if (has_cell) {
+                const int fl = ty * (BX + 1) + tx;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    const Real v = -(FL[m * TL::NFX + fl + 1] - FL[m * TL::NFX + fl]) * idx;
+                    if constexpr (ACC_LDS) slot[m * NCELL] = v;
+                    else accC[m] = v;
+                }
+                if constexpr (MODEL == DIM) srcC = (UHB[fl + 1] - UHB[fl]) * idx;
+            }
+            __syncthreads();
+            // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
+            Real* GL = FB;
+            Real* GR = FB + NC * TL::NFY;
+            if constexpr (CHARV) {
+                for (int t = rt; t < TL::NFY; t += NT) {
+                    const int f = t / BX, i = t - f * BX;
+                    Real wl[NC], wr[NC];
+                    char_face_states<Real, MODEL, 1, TENO>(mat, [&](int q, int m) { return wp(m, i, f - 3 + q); }, weps,
+                                                           wl, wr);
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        GL[m * TL::NFY + t] = wl[m];
+                        GR[m * TL::NFY + t] = wr[m];
+                    }
+                }
+            } else if constexpr (TENO) {
+                // one item = one component of one y face (faces between rows f-1 and f)
+                for (int it = rt; it < NC * TL::NFY; it += NT) {
+                    const int m = it / TL::NFY, t = it - m * TL::NFY;
+                    const int f = t / BX, i = t - f * BX;
+                    const Real* c = &wp(m, i, f - 3);
+                    teno6a_pair(c[0], c[PX], c[2 * PX], c[3 * PX], c[4 * PX], c[5 * PX], weps, GL[it], GR[it]);
+                }
+            } else if constexpr (FV_RECON_ITEMS) {
+                constexpr int NTY = BX * (BY + 2);
+                auto item = [&](int it) {
+                    const int m = it / NTY, t = it - m * NTY;
+                    const int jj = t / BX, i = t - jj * BX, j = jj - 1;
+                    const Real* c = &wp(m, i, j);
+                    Real vm, vp;
+                    weno5z_pair(c[-2 * PX], c[-PX], c[0], c[PX], c[2 * PX], weps, vm, vp);
+                    if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
+                    if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                };
+#pragma unroll FV_RECON_UNROLL
+                for (int it = rt; it < NC * NTY; it += NT) item(it);
+            } else {
+                for (int t = rt; t < BX * (BY + 2); t += NT) {
+                    const int i = t % BX, j = t / BX - 1;
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        Real vm, vp;
+                        weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
+                                    weps, vm, vp);
+                        if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
+                        if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
+                    }
+                }
+            }
+            if constexpr (VISC) {
+                // d/dx of v (c = 0) and u (c = 1) on the y-face region
+                const Real i12 = a.inv12dx;
+                for (int it = rt; it < 2 * TL::RY; it += NT) {
+                    const int c = it >= TL::RY, t = it - c * TL::RY;
+                    const int i = t % BX, j = t / BX - 2;
+                    const int f = V + 1 - c;
+                    DT[it] = dcell(wp(f, i - 2, j), wp(f, i - 1, j), wp(f, i + 1, j), wp(f, i + 2, j), i12);
+                }
+            }
+            __syncthreads();
+            // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
+            for (int t = rt; t < TL::NFY; t += NT) {
+                const int i = t % BX, f = t / BX;
+                Real wl[NC], wr[NC], F[NC], uh;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    wl[m] = GL[m * TL::NFY + t];
+                    wr[m] = GR[m * TL::NFY + t];
+                }
+                if constexpr (POS) {
+                    Real wi[NC], wj[NC];
+#pragma unroll
+                    for (int m = 0; m < NC; m++) {
+                        wi[m] = wp(m, i, f - 1);
+                        wj[m] = wp(m, i, f);
+                    }
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wl[m] = wi[m];
+                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+#pragma unroll
+                        for (int m = 0; m < NC; m++) wr[m] = wj[m];
+                    hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                    if (flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy))
+                        hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
+                } else {
+                    hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
+                }
+                if constexpr (VISC) {
+                    const int r0 = f * BX + i;  // region index of cell f-2
+                    Real Fd[4];
+                    Real muf = a.mu, kf = a.kappa;
+                    if constexpr (VLAW) {
+                        const Real* th = &wp(NC, i, f - 2);
+                        muf = visc_mu(a.vl, ifc(th[0], th[PX], th[2 * PX], th[3 * PX]));
+                        kf = muf * a.vl.kfac;
+                    }
+                    viscous_flux_lds<Real, 1>(&wp(V, i, f - 2), &wp(NC, i, f - 2), PX, PLANE, DT + r0, DZY + r0,
+                                              DT + TL::RY + r0, DZY + TL::RY + r0, BX, muf, kf, a.inv24dy, Fd);
+                    F[V] -= Fd[0];
+                    F[V + 1] -= Fd[1];
+                    F[V + 2] -= Fd[2];
+                    F[P] -= Fd[3];
+                }
+#pragma unroll
+                for (int m = 0; m < NC; m++) GL[m * TL::NFY + t] = F[m];
+                if constexpr (MODEL == DIM) UHB[t] = uh;
+            }
+            __syncthreads();
+            // ---- P6: y divergence of the own cell
+            if (has_cell) {
+                const int fl = ty * BX + tx;
+#pragma unroll
+                for (int m = 0; m < NC; m++) {
+                    const Real d = (GL[m * TL::NFY + fl + BX] - GL[m * TL::NFY + fl]) * idy;
+                    if constexpr (ACC_LDS) slot[m * NCELL] -= d;
+                    else accC[m] -= d;
+                }
+                if constexpr (MODEL == DIM) srcC += (UHB[fl + BX] - UHB[fl]) * idy;
+            }
+        }
+        // rotate carries
+        if constexpr (!ACC_LDS) {
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                accA[m] = accB[m];
+                accB[m] = accC[m];
+            }
+        }
+        srcA = srcB;
+        srcB = srcC;
+        if constexpr (VISC) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                Dc[0][c] = Dc[1][c];
+                Dc[1][c] = Dc[2][c];
+                Dc[2][c] = Dnew[c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NWIN - 1; q++)
+#pragma unroll
+            for (int f = 0; f < NC; f++) win[q][f] = win[q + 1][f];
+    }
+    if (a.inv_max) {
+        // block maximum of the inverse time step, one atomic per workgroup
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem_raw);
+        if ((tid & 63) == 0) red[tid >> 6] = tmax;
+        __syncthreads();
+        if (tid == 0) {
+            double m = red[0];
+            for (int k = 1; k < NT / 64; k++) m = fmax(m, red[k]);
+            atomicMax(a.inv_max, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+__global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+#if FV_KERNARG_INPLACE
+    // the argument block read in place from the kernel-argument segment
+    const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
+    stage_body<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
+#else
+    stage_body<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
+#endif
+}
+
+// Many independent problems in one launch: the workgroups of problem r are
+// first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
+// and limiter setting for every problem of the launch).
+template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+__global__ void __launch_bounds__(NTH, WAVES_PER_EU)
+    batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first, const int n)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = (int)blockIdx.x;
+    if (b >= first[n]) return;
+    int lo = 0, hi = n - 1;  // last r with first[r] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    stage_body<Real, MODEL, POS, REC_WENO_PRIM, false, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    using TL = Tile<Real, MODEL, BX, BY, NTH>;
+    const size_t lds = TL::bytes();
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds,
+                       st, args);
+    return hipGetLastError();
+}
+
+template <typename Real, int MODEL, int REC, bool VLAW>
+static hipError_t launch_pos(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    if (args.positivity) return launch_tile<Real, MODEL, true, REC, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_tile<Real, MODEL, false, REC, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+}
+
+template <typename Real, int MODEL, bool VLAW>
+static hipError_t launch_variant(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    switch (args.recon) {
+    case REC_WENO_CHAR: return launch_pos<Real, MODEL, REC_WENO_CHAR, VLAW>(args, g, st);
+    case REC_TENO_PRIM: return launch_pos<Real, MODEL, REC_TENO_PRIM, VLAW>(args, g, st);
+    case REC_TENO_CHAR: return launch_pos<Real, MODEL, REC_TENO_CHAR, VLAW>(args, g, st);
+    default: return launch_pos<Real, MODEL, REC_WENO_PRIM, VLAW>(args, g, st);
+    }
+}
+
+template <typename Real, int MODEL>
+size_t stage_lds_bytes()
+{
+    return Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>::bytes();
+}
+
+// every variant of one precision and model (explicitly instantiated in fv_stage_inst.hip)
+template <typename Real, int MODEL>
+hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    // a viscosity law is a separate instantiation (viscous model only): the law's
+    // pow() must not weigh on the constant-viscosity kernel
+    if constexpr (MODEL == NS) {
+        if (args.vl.law != 0) return launch_variant<Real, MODEL, true>(args, g, st);
+    }
+    return launch_variant<Real, MODEL, false>(args, g, st);
+}
+
+template <typename Real, int MODEL, bool POS>
+static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, int n, int nblocks, hipStream_t st)
+{
+    using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>;
+    const size_t lds = TL::bytes();
+    auto* k = batch_stage_kernel<Real, MODEL, POS, TILE_BX, TILE_BY, TILE_NT>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (nblocks <= 0) return hipSuccess;  // attribute set-up only
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(TILE_NT), lds, st, args, first, n);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
+                              hipStream_t st)
+{
+    switch (model) {
+    case EULER:
+        return pos ? launch_batch_tile<Real, EULER, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, EULER, false>(args, first, n, nblocks, st);
+    case NS:
+        return pos ? launch_batch_tile<Real, NS, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, NS, false>(args, first, n, nblocks, st);
+    default:
+        return pos ? launch_batch_tile<Real, DIM, true>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, DIM, false>(args, first, n, nblocks, st);
+    }
+}
+
+template <typename Real>
+hipError_t launch_stage(int model, const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+{
+    switch (model) {
+    case EULER: return launch_model<Real, EULER>(args, g, st);
+    case NS: return launch_model<Real, NS>(args, g, st);
+    default: return launch_model<Real, DIM>(args, g, st);
+    }
+}
+
+}  // namespace fv

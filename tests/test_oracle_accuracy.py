@@ -201,7 +201,7 @@ def test_viscous_shear_and_heat_exact_for_quadratics():
     assert np.abs(R2[0][0, inner, :]).max() < 1e-12
 
 
-def _viscous_part(n, law=0, T_ref=1.1, C=0.4):
+def _viscous_part(n, law=0, T_ref=1.1, C=0.4, order=4):
     """R_NS - R_Euler on a smooth periodic field versus exact face fluxes
     (viscosity constant, or the power / Sutherland law of the temperature)."""
     L = 2 * math.pi
@@ -222,7 +222,7 @@ def _viscous_part(n, law=0, T_ref=1.1, C=0.4):
     W[2] = fields["v"](X, Y, Z)
     W[3] = fields["w"](X, Y, Z)
     ns = O.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=O.NS, mu=mu, prandtl=pr, gamma1=g, visc_law=law,
-                  T_ref=T_ref, sutherland=C)
+                  T_ref=T_ref, sutherland=C, visc_order=order)
     eu = O.Config(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, model=O.EULER, gamma1=g)
     U = O.prim_to_cons(ns, W)
     Rv = O.rhs(ns, U) - O.rhs(eu, U)
@@ -261,6 +261,41 @@ def test_viscous_flux_fourth_order_against_exact_fluxes(law):
     (Sec. 2.5) evaluated at the interpolated face temperature."""
     e1, e2 = _viscous_part(16, law), _viscous_part(32, law)
     assert math.log2(e1 / e2) > 3.6, (e1, e2)
+
+
+@pytest.mark.parametrize("law", [0, 2])
+def test_viscous_flux_sixth_order_against_exact_fluxes(law):
+    """The 6th-order central viscous fluxes of the paper's single-phase setup."""
+    e1, e2 = _viscous_part(16, law, order=6), _viscous_part(32, law, order=6)
+    assert math.log2(e1 / e2) > 5.5, (e1, e2)
+    assert e2 < _viscous_part(32, law) / 10.0
+
+
+def test_sixth_order_viscous_stencils_exact_for_quintics():
+    """u = quintic in y: the 6-cell face derivative and interpolation are exact, so
+    the momentum and energy RHS equal the difference quotients of the exact face
+    fluxes mu u'(y) and mu u(y) u'(y)."""
+    n, h = 20, 0.1
+    mu, pr, g = 0.03, 0.7, 1.4
+    y = (np.arange(n) + 0.5) * h
+    coef = [0.3, -0.5, 0.7, -0.2, 0.05, 0.01]
+    u = sum(cf * y ** k for k, cf in enumerate(coef))
+    du = lambda s: sum(k * cf * s ** (k - 1) for k, cf in enumerate(coef) if k)
+    uu = lambda s: sum(cf * s ** k for k, cf in enumerate(coef))
+    W = np.zeros((5, 1, n, 6))
+    W[0] = 1.0
+    W[1] = u[None, :, None]
+    W[4] = 1.0
+    bc = (O.PERIODIC, O.PERIODIC, O.ZERO_GRADIENT, O.ZERO_GRADIENT, O.PERIODIC, O.PERIODIC)
+    cfg = O.Config(nx=6, ny=n, nz=1, dx=h, dy=h, dz=h, model=O.NS, bc=bc, mu=mu, prandtl=pr, gamma1=g,
+                   visc_order=6)
+    R = O.rhs(cfg, O.prim_to_cons(cfg, W))
+    inner = slice(5, n - 5)
+    yl, yr = y - h / 2, y + h / 2
+    RM = mu * (du(yr) - du(yl)) / h
+    RE = mu * (uu(yr) * du(yr) - uu(yl) * du(yl)) / h
+    assert np.allclose(R[1][0, inner, :], RM[inner, None], rtol=1e-10, atol=1e-12)
+    assert np.allclose(R[4][0, inner, :], RE[inner, None], rtol=1e-10, atol=1e-12)
 
 
 def test_viscosity_laws_reduce_to_constant_at_reference_temperature():
