@@ -46,7 +46,7 @@ class _Cfg(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("visc_law", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
-        ("visc_order", ctypes.c_int32), ("pad3_", ctypes.c_int32),
+        ("visc_order", ctypes.c_int32), ("thinc", ctypes.c_int32),
     ]
 
 
@@ -76,6 +76,7 @@ class Config:
     visc_law: int = 0             # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
     scheme: int = 0               # 0: WENO5-Z, 1: TENO6-A (Sec. 3.2 step 3)
     visc_order: int = 4           # central viscous stencils: 4th or 6th order
+    thinc: int = 0                # 1: THINC volume-fraction faces in interface cells (DIM)
     T_ref: float = 1.0
     sutherland: float = 0.0
     gas_R: float = 1.0
@@ -107,6 +108,7 @@ class Config:
         c.visc_law = self.visc_law
         c.scheme = self.scheme
         c.visc_order = self.visc_order
+        c.thinc = self.thinc
         c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
         return c
 
@@ -126,6 +128,7 @@ def lib():
         L.orc_weno5z.restype = ctypes.c_double
         L.orc_teno6a_parts.argtypes = [dp, ctypes.c_double, dp]
         L.orc_teno6a_parts.restype = ctypes.c_double
+        L.orc_thinc_faces.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
         L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
         L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double]
@@ -173,6 +176,14 @@ def cons_to_prim(cfg: Config, U) -> np.ndarray:
 
 def weno5z(a, b, c, d, e, eps=1e-40) -> float:
     return lib().orc_weno5z(a, b, c, d, e, eps)
+
+
+def thinc_faces(abar, theta, beta):
+    """THINC profile of a cell with mean abar: (value at the -d face, value at the
+    +d face, interface centre x_c)."""
+    out = np.zeros(3)
+    lib().orc_thinc_faces(float(abar), float(theta), float(beta), _dp(out))
+    return tuple(out)
 
 
 TENO_PARTS = ("beta0", "beta1", "beta2", "beta3", "beta6", "tau6", "CT", "delta0", "delta1", "delta2", "delta3",

@@ -30,6 +30,8 @@
  *  - the flux limiter's pseudo-time state is the split forward-Euler state
  *    U_i -/+ 2 D (dt/dx) (F_face - F(U_i));
  *  - CFL: dt = CFL * min(min_d dx_d/(|u_d|+c), (3/14) rho dx_min^2 / mu);
+ *  - THINC: see thinc_state (sign of the profile, blank interface centre,
+ *    partial densities from the cell's phase densities);
  *  - TENO6-A: the paper fixes its stencils (figure of the reconstruction
  *    schematic) and defers its weights to the cited scheme; this oracle takes
  *    Jiang-Shu indicators, tau_6 = |beta_6 - (beta_0 + 4 beta_1 + beta_2)/6|,
@@ -72,7 +74,7 @@ typedef struct {
     double sutherland;   /* Sutherland's constant C */
     double gas_R;        /* specific gas constant, T = p / (rho R) */
     int32_t visc_order;  /* order of the central viscous stencils: 4 (0 selects 4) or 6 */
-    int32_t pad3_;
+    int32_t thinc;       /* 1: THINC volume-fraction faces in interface cells (DIM, Sec. 3.2) */
 } orc_cfg;
 
 #define NH 3   /* halo width: WENO5 at face i-1/2 reads cells i-3 .. i+2 */
@@ -323,17 +325,23 @@ double orc_teno6a_parts(const double *v, double eps, double *parts)
             + 0.25 * (b - d) * (b - d);
     beta[2] = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e)
             + 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
-    beta[3] = (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f)
-             + d * (11003.0 * d - 17246.0 * e + 4642.0 * f)
-             + e * (7043.0 * e - 3882.0 * f)
-             + 547.0 * f * f) / 240.0;
-    double beta6 = (a * (271779.0 * a - 2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e
-                         - 245620.0 * f)
-                  + b * (5653317.0 * b - 20427884.0 * c + 17905032.0 * d - 7727988.0 * e + 1325006.0 * f)
-                  + c * (19510972.0 * c - 35817664.0 * d + 15929912.0 * e - 2792660.0 * f)
-                  + d * (17195652.0 * d - 15880404.0 * e + 2863984.0 * f)
-                  + e * (3824847.0 * e - 1429976.0 * f)
-                  + 139633.0 * f * f) / 120960.0;
+    /* beta_3 and beta_6 as quadratic forms in the data; the indicators see
+     * derivatives only (adding a constant to the data leaves them unchanged), so
+     * the forms are evaluated on values relative to v_i, whose own entries drop
+     * out: evaluated on the raw values the large coefficients cancel to
+     * round-off on nearly constant data */
+    double A = a - c, B = b - c, C = 0.0, D = d - c, E = e - c, F = f - c;
+    beta[3] = (C * (2107.0 * C - 9402.0 * D + 7042.0 * E - 1854.0 * F)
+             + D * (11003.0 * D - 17246.0 * E + 4642.0 * F)
+             + E * (7043.0 * E - 3882.0 * F)
+             + 547.0 * F * F) / 240.0;
+    double beta6 = (A * (271779.0 * A - 2380800.0 * B + 4086352.0 * C - 3462252.0 * D + 1458762.0 * E
+                         - 245620.0 * F)
+                  + B * (5653317.0 * B - 20427884.0 * C + 17905032.0 * D - 7727988.0 * E + 1325006.0 * F)
+                  + C * (19510972.0 * C - 35817664.0 * D + 15929912.0 * E - 2792660.0 * F)
+                  + D * (17195652.0 * D - 15880404.0 * E + 2863984.0 * F)
+                  + E * (3824847.0 * E - 1429976.0 * F)
+                  + 139633.0 * F * F) / 120960.0;
     /* step 3 */
     double tau = fabs(beta6 - (beta[0] + 4.0 * beta[1] + beta[2]) / 6.0);
     /* step 4 */
@@ -800,6 +808,69 @@ void orc_char_matrices(const orc_cfg *c, int d, const double *W, double *K, doub
         }
 }
 
+/* ------------------------------------------------------------------------ */
+/* THINC interface capturing (Sec. 3.2, the step after the reconstruction;  */
+/* five-equation model).  In an interface cell (eps <= alpha_i <= 1 - eps,   */
+/* eps = 1e-4, and alpha monotone through the cell along d) the volume       */
+/* fraction follows (1 + theta tanh(beta_i (xt + x_c))) / 2 over the cell,   */
+/* xt = (x - x_{i-1/2}) / dx in [0, 1], with beta_i = beta |n_d| + 0.01,     */
+/* beta = 1, n = grad alpha / |grad alpha| (second-order central             */
+/* differences), theta = sgn(alpha_{i+1} - alpha_{i-1}).  Readings: the      */
+/* printed profile has no theta (it could not follow a decreasing           */
+/* interface) and its centre x_c is left blank; x_c is fixed here by the     */
+/* profile's cell average being alpha_i, which gives in closed form          */
+/*   tanh(beta x_c) = (exp(theta beta (2 alpha_i - 1)) - cosh beta) / sinh beta. */
+/* The faces then take the profile's values at xt = 0 and 1; the partial    */
+/* densities follow as alpha_k rho_k with the cell's phase densities        */
+/* rho_k; velocity and pressure keep the shock-capturing values.            */
+/* ------------------------------------------------------------------------ */
+#define THINC_EPS 1.0e-4
+#define THINC_BETA 1.0
+
+/* face values of the THINC profile of a cell with mean abar: out[0] at xt = 0,
+ * out[1] at xt = 1, out[2] = x_c (exported for the tests) */
+void orc_thinc_faces(double abar, double theta, double beta, double *out)
+{
+    double Q = exp(theta * beta * (2.0 * abar - 1.0));
+    double T = (Q - cosh(beta)) / sinh(beta);   /* tanh(beta x_c) */
+    double xc = atanh(T) / beta;
+    out[0] = 0.5 * (1.0 + theta * tanh(beta * xc));
+    out[1] = 0.5 * (1.0 + theta * tanh(beta * (1.0 + xc)));
+    out[2] = xc;
+}
+
+/* interface-cell test on alpha_{i-1}, alpha_i, alpha_{i+1} */
+static int thinc_cell(double am, double a0, double ap)
+{
+    return a0 >= THINC_EPS && a0 <= 1.0 - THINC_EPS && (ap - a0) * (a0 - am) > 0.0;
+}
+
+/* THINC face value of cell (i,j,k) on its face towards side (0: -d, 1: +d); its
+ * state W is overwritten in the volume fraction and partial densities */
+static void thinc_state(const orc_cfg *c, const padded *p, int d, int i, int j, int k, int side, double *W)
+{
+    double h[3] = {c->dx, c->dy, c->dz};
+    double g[3], gn = 0.0;
+    for (int e = 0; e < 3; e++) {
+        const int *o = DI[e];
+        g[e] = (get_q(p, 6, i + o[0], j + o[1], k + o[2]) - get_q(p, 6, i - o[0], j - o[1], k - o[2])) / (2.0 * h[e]);
+        gn += g[e] * g[e];
+    }
+    const int *o = DI[d];
+    double am = get_q(p, 6, i - o[0], j - o[1], k - o[2]);
+    double a0 = get_q(p, 6, i, j, k);
+    double ap = get_q(p, 6, i + o[0], j + o[1], k + o[2]);
+    double theta = ap > am ? 1.0 : -1.0;
+    double beta = THINC_BETA * fabs(g[d]) / sqrt(gn) + 0.01;
+    double f[3];
+    orc_thinc_faces(a0, theta, beta, f);
+    double rho1 = get_q(p, 0, i, j, k) / a0, rho2 = get_q(p, 1, i, j, k) / (1.0 - a0);
+    double af = f[side];
+    W[6] = af;
+    W[0] = af * rho1;
+    W[1] = (1.0 - af) * rho2;
+}
+
 static void face_flux(const orc_cfg *c, const padded *p, int d, int i, int j, int k, double dt,
                       double *F, double *uh, int *flags)
 {
@@ -811,6 +882,12 @@ static void face_flux(const orc_cfg *c, const padded *p, int d, int i, int j, in
     for (int s = 0; s < 6; s++)
         get_w(p, i + (s - 2) * o[0], j + (s - 2) * o[1], k + (s - 2) * o[2], v[s]);
     reconstruct(c, d, v, WL, WR);
+    /* THINC in interface cells: the left state from cell i (its +d face), the
+     * right state from cell i+1 (its -d face) */
+    if (c->model == M_DIM && c->thinc) {
+        if (thinc_cell(v[1][6], v[2][6], v[3][6])) thinc_state(c, p, d, i, j, k, 1, WL);
+        if (thinc_cell(v[2][6], v[3][6], v[4][6])) thinc_state(c, p, d, i + o[0], j + o[1], k + o[2], 0, WR);
+    }
     double Wi[MAXC], Wip[MAXC];
     get_w(p, i, j, k, Wi);
     get_w(p, i + o[0], j + o[1], k + o[2], Wip);
