@@ -35,15 +35,28 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 # Algorithmic floating-point operations per cell per stage (+ - * / sqrt min
-# max abs each count 1), from the formulas of the scheme:
+# max abs and comparisons each count 1), from the formulas of the scheme:
 #   WENO5-Z pair (both face values of a cell, one component, one direction): 95
-#   HLLC face: 91;  viscous face: 80;  cell-centred derivatives: 9 x 5;
+#   one-sided WENO5-Z value: 72;  TENO6-A face (both states, shared cut-off): 389
+#   characteristic projection of a face: 30 + 12 per projected field + 6 per component
+#   HLLC face: 91;  viscous face: 80 (sixth order: 120);  cell-centred derivatives: 9 x 5;
 #   U -> W: 13 (+1 for T = p/rho);  divergence: 9 per component;  Shu-Osher combine: 5 per component.
-def flops_per_cell(model: int) -> int:
+def flops_per_cell(model: int, recon: int = 0, scheme: int = 0, visc_order: int = 4) -> int:
     nc = 7 if model == 2 else 5
-    weno = 95 * nc * 3
+    if scheme == 1:
+        per_face = 389 * nc
+    elif recon == 1:
+        per_face = 2 * 72 * nc
+    else:
+        per_face = 95 * nc
+    if recon == 1:
+        per_face += 30 + 12 * (2 + (2 if model == 2 else 1)) + 6 * nc
+    weno = per_face * 3
     hllc = 91 * 3 + (2 * 3 * 3 if model == 2 else 0)
     visc = (80 * 3 + 45) if model == 1 else 0
+    if model == 1 and visc_order == 6:
+        # separate passes: q (13), gradient (9 x 9), two faces per direction (2 x 3 x 120) + divergence (12)
+        visc = 13 + 81 + 720 + 12
     conv = 13 + (1 if model == 1 else 0) + (10 if model == 2 else 0)
     div = 9 * nc + (7 if model == 2 else 0)
     rk = 5 * nc
@@ -55,7 +68,7 @@ PROFILE_MD = os.path.join(ROOT, "profiles", "stage_kernel_ns_tgv256_f64.md")
 
 # the benchmarked instantiation: stage_kernel<double, NS, positivity off, primitive
 # reconstruction, constant viscosity, 16x16 tile, 256 threads>
-STAGE_KERNEL_SYMBOL = "_ZN2fv12stage_kernelIdLi1ELb0ELb0ELb0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE"
+STAGE_KERNEL_SYMBOL = "_ZN2fv12stage_kernelIdLi1ELb0ELi0ELi0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE"
 
 
 def _elf_sections(elf: bytes):
@@ -268,6 +281,13 @@ def main():
     ap.add_argument("--model", choices=["ns", "euler", "dim"], default="ns")
     ap.add_argument("--recon", type=int, choices=[0, 1], default=0,
                     help="reconstruction variables: 0 primitive (the benchmark), 1 characteristic")
+    ap.add_argument("--scheme", type=int, choices=[0, 1], default=0,
+                    help="reconstruction scheme: 0 WENO5-Z (the benchmark), 1 TENO6-A")
+    ap.add_argument("--thinc", type=int, choices=[0, 1], default=0,
+                    help="five-equation model: THINC interface capturing (1) or not (0, the benchmark)")
+    ap.add_argument("--visc-order", type=int, choices=[4, 6], default=4,
+                    help="central viscous stencils of the NS model: 4 (fused, the benchmark) or 6 "
+                         "(separate passes; timed per fixed-dt step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of known size first (for HBM counter scaling)")
@@ -296,20 +316,26 @@ def main():
     if model == S.DIM:
         case = WL.shock_bubble(2 * args.n if args.n < 256 else 256, args.n // 2 if args.n < 256 else 128,
                                args.n // 2 if args.n < 256 else 128, with_field=False)
-        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon, scheme=args.scheme,
+                                     visc_order=args.visc_order if model == S.NS else 0, thinc=args.thinc)
         rho2, u2, p2 = case.meta["post_shock"]
         H = case.meta["H"]
         params = [0.060, 0.090, H / 2, H / 2, 0.25 * H, WL.ALPHA_EPS, rho2, u2, p2, 1.2041, 101325.0, 0.1660]
         case_id = S.CASE_SBI
-        workload = f"DIM shock-bubble Ma 1.22 air/He {cfg.nx}x{cfg.ny}x{cfg.nz}, limiters on, CFL 0.5"
+        workload = (f"DIM shock-bubble Ma 1.22 air/He {cfg.nx}x{cfg.ny}x{cfg.nz}, limiters on, CFL 0.5"
+                    f"{', characteristic reconstruction' if args.recon else ''}"
+                    f"{', TENO6-A' if args.scheme else ''}{', THINC' if args.thinc else ''}")
     else:
         case = WL.taylor_green(args.n, viscous=(model == S.NS), with_field=False)
-        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon)
+        cfg = S.config_from_case(case, dtype=dtype, cfl=0.5, recon=args.recon, scheme=args.scheme,
+                                     visc_order=args.visc_order if model == S.NS else 0)
         params = [0.1, 1.0, 1e-3]
         case_id = S.CASE_TGV
         workload = (f"{'NS' if model == S.NS else 'Euler'} Taylor-Green vortex Ma 0.1"
                     f"{' Re 1600 Pr 0.72' if model == S.NS else ''} periodic {args.n}^3, CFL 0.5"
-                    f"{', characteristic reconstruction' if args.recon else ''}")
+                    f"{', characteristic reconstruction' if args.recon else ''}"
+                    f"{', TENO6-A' if args.scheme else ''}"
+                    f"{', 6th-order viscous fluxes' if cfg.visc_order == 6 else ''}")
 
     if args.copy_calibration:
         nbytes = 1 << 30
@@ -329,6 +355,17 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(events=None):
+        if cfg.visc_order == 6:
+            # sixth-order viscous passes + stage, three times, at the first step's dt
+            if events is not None:
+                events[0][0].record(stream)
+            S.rk3_step(cfg, U, dt_fixed, ws)
+            if events is not None:
+                events[0][1].record(stream)
+                for k in (1, 2):
+                    events[k][0].record(stream)
+                    events[k][1].record(stream)
+            return
         # stage 1, stage 2, stage 3 fused with the CFL reduction that yields the next dt
         for k in range(3):
             if events is not None:
@@ -343,6 +380,7 @@ def main():
                 events[k][1].record(stream)
 
     S.compute_dt(cfg, U, dt_dev, ws)
+    dt_fixed = float(dt_dev.item())
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -366,7 +404,7 @@ def main():
     value = ncell * 3 * args.steps / (ms_total * 1e-3)
 
     es = 8 if dtype == S.F64 else 4
-    fpc = flops_per_cell(model)
+    fpc = flops_per_cell(model, args.recon, args.scheme, cfg.visc_order)
     flops_launch = fpc * ncell
     achieved_tflops = flops_launch / (mean_stage_ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if dtype == S.F64 else PEAK_FP32_TFLOPS
@@ -374,7 +412,11 @@ def main():
     hbm_gbs = alg_bytes / (mean_stage_ms * 1e-3) / 1e9
 
     finite = bool(torch.isfinite(U).all().item())
-    workload_key = f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
+    default_kernel = (model == S.NS and dtype == S.F64 and args.recon == 0 and args.scheme == 0
+                      and cfg.visc_order != 6)
+    workload_key = (f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
+                    + ("-teno" if args.scheme else "") + ("-v6" if cfg.visc_order == 6 else "")
+                    + ("-thinc" if args.thinc else ""))
     traffic = measured_traffic(workload_key)
     out = {
         "metric": "cell-updates/s + % HBM roofline (RK3 stage, 256^3); batched p50/p99 latency",
@@ -396,7 +438,7 @@ def main():
                      "stage2": sum(stage_ms[1]) / args.steps, "stage3": sum(stage_ms[2]) / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak, "traffic": traffic,
-                     "kernel": "stage_kernel", "flops_per_cell": fpc, "kernel_fingerprint": stage_kernel_hash()},
+                     "kernel": "stage_kernel", "flops_per_cell": fpc, "kernel_fingerprint": stage_kernel_hash() if default_kernel else None},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell},
         "wall_s": wall,

@@ -8,9 +8,10 @@
  *   FV_EULER  single-phase inviscid       (Sec. 2.1, 3.5)
  *   FV_NS     single-phase viscous        (Sec. 2.1 dissipative fluxes, Sec. 2.5)
  *   FV_DIM    five-equation diffuse-interface two-phase model (Sec. 2.3, 3.6)
- * with WENO5-Z reconstruction of primitive variables, the HLLC flux,
- * 4th-order central viscous fluxes and, optionally (default for FV_DIM), the
- * interpolation and flux positivity limiters of Sec. 3.3.
+ * with WENO5-Z or TENO6-A reconstruction of primitive or characteristic
+ * variables, the HLLC flux, 4th-order central viscous fluxes and, optionally
+ * (default for FV_DIM), the interpolation and flux positivity limiters of
+ * Sec. 3.3.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -42,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FV_ABI_VERSION 2
+#define FV_ABI_VERSION 3
 
 enum fv_model { FV_EULER = 0, FV_NS = 1, FV_DIM = 2 };
 enum fv_dtype { FV_F64 = 0, FV_F32 = 1 };
@@ -103,10 +104,23 @@ typedef struct fv_config {
                             mu (T/T_ref)^1.5 (T_ref + C)/(T + C); mu = the value at
                             T_ref.  Faces use the temperature interpolated to the face;
                             conductivity from the constant Prandtl number          */
-    int32_t reserved;    /* must be 0                                      */
+    int32_t scheme;      /* reconstruction scheme (Sec. 3.2 step 3): 0 WENO5-Z; 1 TENO6-A
+                            (stencils of the reconstruction schematic, Jiang-Shu
+                            indicators, adaptive cut-off; the six cells i-2..i+3
+                            of a face for both states); batches and the adjoint
+                            take 0 only                                         */
     double T_ref;        /* reference temperature of the law, > 0 when visc_law != 0 */
     double sutherland;   /* Sutherland's constant C, >= 0                  */
     double gas_R;        /* specific gas constant in T = p / (rho R); 0 selects 1 */
+    int32_t visc_order;  /* central viscous stencils (FV_NS): 0 or 4 -- 4th order inside
+                            the fused stage; 6 -- 6th order (the paper's single-phase
+                            simulation setup), computed by separate passes into the workspace
+                            (rhs_ws, rk3_stage3_cfl, rk3_step, advance; not rhs,
+                            rk3_stage or batches)                               */
+    int32_t thinc;       /* FV_DIM: 1 replaces the volume fraction and partial densities of
+                            the face states of interface cells by the THINC profile
+                            (Sec. 3.2; eps 1e-4, beta 1; profile centre from the cell
+                            average); 0 off.  Not in batches                    */
 } fv_config;
 
 /* Result of check_state. */
@@ -119,8 +133,10 @@ typedef struct fv_report {
 /* Number of components for cfg->model (5 or 7), or a negative status. */
 int32_t fv_ncomp(const fv_config* cfg);
 
-/* Bytes of workspace needed by rk3_step / advance / compute_dt /
- * check_state: two extra state arrays plus 256 bytes of device scalars. */
+/* Bytes of workspace needed by rhs_ws / rk3_step / advance / compute_dt /
+ * check_state: two extra state arrays plus 256 bytes of device scalars; with
+ * visc_order 6 also the viscous passes' fields, 13 (nx+6)(ny+6)(nz+6) + 4 nx ny nz
+ * values (each block aligned to 256 bytes). */
 int workspace_bytes(const fv_config* cfg, size_t* out);
 
 /* Analytic initial condition at cell centres, written as conservative
@@ -139,6 +155,11 @@ int cons_to_prim(const fv_config* cfg, const void* U, void* W, void* stream);
  * dt is used only by the flux limiter's admissibility test (ignored when the
  * limiters are off).  U and R must not overlap. */
 int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
+
+/* rhs with a workspace of workspace_bytes(cfg) bytes (required for
+ * visc_order 6, whose viscous passes keep their intermediate fields there;
+ * otherwise the same as rhs).  The workspace contents are overwritten. */
+int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, void* stream);
 
 /* One TVD-RK3 stage (Sec. 3.4), the benchmarked unit:
  *   stage 1: Uout = Un + dt R(Un)                        (Uk must equal Un)

@@ -11,7 +11,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvrk3.so")
-SOURCES = ["fv_stage.hip", "fv_aux.hip", "fv_adjoint.hip", "fv_api.hip"]
+# (source, defines): the stage kernels compile per precision and model so that
+# the units build in parallel
+UNITS = [("fv_stage_inst.hip", (f"-DFV_REAL={r}", f"-DFV_MODEL={m}"))
+         for r in ("double", "float") for m in ("NS", "EULER", "DIM")] + [
+    ("fv_stage_launch.hip", ()), ("fv_visc6.hip", ()), ("fv_aux.hip", ()), ("fv_adjoint.hip", ()),
+    ("fv_api.hip", ())]
+SOURCES = sorted({u[0] for u in UNITS})
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -19,7 +25,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # keep the compiler from forming packed FP32 VALU operations
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # fused multiply-adds only where one source expression has the a*b+c form:
@@ -31,13 +36,37 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None,
+          jobs: int | None = None) -> str:
+    """Compile every unit to an object (in parallel), then link the shared library."""
     out = out or LIB
+    objdir = out + ".objs"
+    os.makedirs(objdir, exist_ok=True)
+    jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 8))
+    cmds = []
+    for src, defs in UNITS:
+        tag = "".join(d.split("=")[1][0].lower() for d in defs)
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
+        cmds.append((obj, [HIPCC, *FLAGS, *(extra or []), *defs, "-c", os.path.join(CSRC, src), "-o", obj]))
+    pending = list(cmds)
+    running = []
+    failed = []
+    while pending or running:
+        while pending and len(running) < jobs:
+            obj, cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((obj, subprocess.Popen(cmd)))
+        obj, proc = running.pop(0)
+        if proc.wait() != 0:
+            failed.append(obj)
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(os.path.basename(f) for f in failed)})")
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(extra or []), "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in cmds]]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, out)
     return out
 

@@ -40,6 +40,21 @@ size_t state_bytes(const fv_config* c)
 
 constexpr size_t SCALAR_BYTES = 256;  // dt, inverse-dt max, time accumulator, check words
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool visc6(const fv_config* c) { return c->model == FV_NS && c->visc_order == 6; }
+
+long long padded_cells(const fv_config* c) { return (long long)(c->nx + 6) * (c->ny + 6) * (c->nz + 6); }
+
+// workspace of the sixth-order viscous passes: q [4][npad], gradient [9][npad], divergence [4][ncell]
+size_t visc6_bytes(const fv_config* c)
+{
+    if (!visc6(c)) return 0;
+    const size_t es = c->dtype == FV_F64 ? 8 : 4;
+    const size_t np = (size_t)padded_cells(c), n = (size_t)c->nx * c->ny * c->nz;
+    return align256(4 * np * es) + align256(9 * np * es) + align256(4 * n * es);
+}
+
 int validate(const fv_config* c)
 {
     if (!c) return fail(FV_ENULL, "cfg is NULL");
@@ -49,7 +64,7 @@ int validate(const fv_config* c)
     if (c->model < FV_EULER || c->model > FV_DIM) return fail(FV_EINVAL, "model %d unknown", c->model);
     if (c->dtype != FV_F64 && c->dtype != FV_F32) return fail(FV_EINVAL, "dtype %d unknown", c->dtype);
     if (c->recon != 0 && c->recon != 1) return fail(FV_EINVAL, "recon must be 0 or 1");
-    if (c->reserved != 0) return fail(FV_EINVAL, "reserved must be 0");
+    if (c->scheme != 0 && c->scheme != 1) return fail(FV_EINVAL, "scheme must be 0 (WENO5-Z) or 1 (TENO6-A)");
     if (c->visc_law < 0 || c->visc_law > 2) return fail(FV_EINVAL, "visc_law %d unknown", c->visc_law);
     if (c->visc_law != 0) {
         if (c->model != FV_NS) return fail(FV_EINVAL, "viscosity laws apply to the viscous model");
@@ -57,6 +72,11 @@ int validate(const fv_config* c)
         if (!(c->sutherland >= 0)) return fail(FV_EINVAL, "sutherland must be >= 0");
     }
     if (!(c->gas_R >= 0)) return fail(FV_EINVAL, "gas_R must be >= 0");
+    if (c->visc_order != 0 && c->visc_order != 4 && c->visc_order != 6)
+        return fail(FV_EINVAL, "visc_order must be 0, 4 or 6");
+    if (c->visc_order == 6 && c->model != FV_NS) return fail(FV_EINVAL, "visc_order 6 applies to the viscous model");
+    if (c->thinc != 0 && c->thinc != 1) return fail(FV_EINVAL, "thinc must be 0 or 1");
+    if (c->thinc && c->model != FV_DIM) return fail(FV_EINVAL, "thinc applies to the five-equation model");
     const int n3[3] = {c->nx, c->ny, c->nz};
     for (int a = 0; a < 3; a++) {
         for (int s = 0; s < 2; s++) {
@@ -162,7 +182,8 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.nchunks = (c->nz + zc - 1) / zc;
     g.nblocks = (int)(tiles * a.nchunks);
     a.positivity = positivity_on(c) ? 1 : 0;
-    a.recon = c->recon;
+    a.recon = c->recon + 2 * c->scheme;  // REC_* variant
+    a.thinc = c->model == FV_DIM ? c->thinc : 0;
     a.ndim = (c->nx > 1) + (c->ny > 1) + (c->nz > 1);
     a.mat = material<Real>(c);
     a.tol.eps_rho = (Real)(c->eps_rho > 0 ? c->eps_rho : (f64 ? 1e-12 : 1e-10));
@@ -188,31 +209,6 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     return a;
 }
 
-template <typename Real>
-int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt, const double* dt_dev,
-               hipStream_t st, unsigned long long* inv_max)
-{
-    fv::LaunchGeom g;
-    fv::StageArgs<Real> a = stage_args<Real>(c, g);
-    a.inv_max = inv_max;
-    a.Uk = (const Real*)Uk;
-    a.Un = (const Real*)Un;
-    a.out = (Real*)out;
-    a.dt = dt;
-    a.dt_dev = dt_dev;
-    a.mode = mode;
-    hipError_t e = fv::launch_stage<Real>(c->model, a, g, st);
-    if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
-    return FV_OK;
-}
-
-int stage_dispatch(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt,
-                   const double* dt_dev, hipStream_t st, unsigned long long* inv_max = nullptr)
-{
-    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max);
-    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max);
-}
-
 struct WsLayout {
     char* A;
     char* B;
@@ -220,6 +216,9 @@ struct WsLayout {
     unsigned long long* inv_max;
     double* t_acc;
     long long* check;
+    char* vq;  // sixth-order viscous passes (null otherwise)
+    char* vg;
+    char* vr;
 };
 
 WsLayout ws_layout(const fv_config* c, void* ws)
@@ -233,7 +232,59 @@ WsLayout ws_layout(const fv_config* c, void* ws)
     w.inv_max = (unsigned long long*)(sc + 8);
     w.t_acc = (double*)(sc + 16);
     w.check = (long long*)(sc + 32);
+    w.vq = w.vg = w.vr = nullptr;
+    if (visc6(c)) {
+        const size_t es = c->dtype == FV_F64 ? 8 : 4;
+        const size_t np = (size_t)padded_cells(c);
+        w.vq = sc + SCALAR_BYTES;
+        w.vg = w.vq + align256(4 * np * es);
+        w.vr = w.vg + align256(9 * np * es);
+    }
     return w;
+}
+
+template <typename Real>
+int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt, const double* dt_dev,
+               hipStream_t st, unsigned long long* inv_max, const WsLayout* w)
+{
+    fv::LaunchGeom g;
+    fv::StageArgs<Real> a = stage_args<Real>(c, g);
+    if (visc6(c)) {
+        if (!w) return fail(FV_EUNSUPPORTED, "sixth-order viscous fluxes need a workspace");
+        fv::Visc6Args<Real> v;
+        v.nx = c->nx;
+        v.ny = c->ny;
+        v.nz = c->nz;
+        for (int k = 0; k < 6; k++) v.bc[k] = c->bc[k];
+        v.ncell = (long long)c->nx * c->ny * c->nz;
+        v.npad = padded_cells(c);
+        v.mat = a.mat;
+        v.vl = a.vl;
+        v.ih[0] = (Real)(1.0 / c->dx);
+        v.ih[1] = (Real)(1.0 / c->dy);
+        v.ih[2] = (Real)(1.0 / c->dz);
+        hipError_t e = fv::launch_visc6<Real>(v, (const Real*)Uk, (Real*)w->vq, (Real*)w->vg, (Real*)w->vr, st);
+        if (e != hipSuccess) return hip_fail(e, "viscous passes");
+        a.rvisc = (const Real*)w->vr;
+    }
+    a.inv_max = inv_max;
+    a.Uk = (const Real*)Uk;
+    a.Un = (const Real*)Un;
+    a.out = (Real*)out;
+    a.dt = dt;
+    a.dt_dev = dt_dev;
+    a.mode = mode;
+    hipError_t e = fv::launch_stage<Real>(c->model, a, g, st);
+    if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+    return FV_OK;
+}
+
+int stage_dispatch(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt,
+                   const double* dt_dev, hipStream_t st, unsigned long long* inv_max = nullptr,
+                   const WsLayout* w = nullptr)
+{
+    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w);
+    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w);
 }
 
 }  // namespace
@@ -252,7 +303,7 @@ int workspace_bytes(const fv_config* cfg, size_t* out)
     int r = validate(cfg);
     if (r) return r;
     if (!out) return fail(FV_ENULL, "out is NULL");
-    *out = 2 * ((state_bytes(cfg) + 255) & ~(size_t)255) + SCALAR_BYTES;
+    *out = 2 * ((state_bytes(cfg) + 255) & ~(size_t)255) + SCALAR_BYTES + visc6_bytes(cfg);
     return FV_OK;
 }
 
@@ -315,7 +366,19 @@ int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream)
     if ((r = check_ptr(U, "U")) || (r = check_ptr(R, "R"))) return r;
     if (U == R) return fail(FV_EINVAL, "U and R must not overlap");
     if (!(dt >= 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and >= 0");
+    if (visc6(cfg)) return fail(FV_EUNSUPPORTED, "visc_order 6 needs a workspace: call rhs_ws");
     return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, (hipStream_t)stream);
+}
+
+int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(U, "U")) || (r = check_ptr(R, "R")) || (r = check_ptr(ws, "ws"))) return r;
+    if (U == R) return fail(FV_EINVAL, "U and R must not overlap");
+    if (!(dt >= 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and >= 0");
+    const WsLayout w = ws_layout(cfg, ws);
+    return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, (hipStream_t)stream, nullptr, &w);
 }
 
 int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* Uk, void* Uout, double dt,
@@ -328,6 +391,7 @@ int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* U
     if (Uk == Uout) return fail(FV_EINVAL, "Uout must not overlap Uk");
     if (stage == 1 && Un != Uk) return fail(FV_EINVAL, "stage 1 needs Uk == Un");
     if (!dt_dev && (!(dt > 0) || !isfinite(dt))) return fail(FV_EINVAL, "dt must be finite and > 0");
+    if (visc6(cfg)) return fail(FV_EUNSUPPORTED, "visc_order 6 needs a workspace: use rk3_stage3_cfl, rk3_step or advance");
     return stage_dispatch(cfg, stage, Un, Uk, Uout, dt, dt_dev, (hipStream_t)stream);
 }
 
@@ -346,7 +410,7 @@ int rk3_stage3_cfl(const fv_config* cfg, const void* Un, const void* Uk, void* U
     const WsLayout w = ws_layout(cfg, ws);
     hipError_t e = fv::launch_reset_max(w.inv_max, st);
     if (e != hipSuccess) return hip_fail(e, "rk3_stage3_cfl: reset");
-    if ((r = stage_dispatch(cfg, 3, Un, Uk, Uout, 0.0, dt_dev, st, w.inv_max))) return r;
+    if ((r = stage_dispatch(cfg, 3, Un, Uk, Uout, 0.0, dt_dev, st, w.inv_max, &w))) return r;
     e = fv::launch_dt_finish(w.inv_max, cfg->cfl, dt_next, nullptr, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "rk3_stage3_cfl: finish");
     return FV_OK;
@@ -356,9 +420,9 @@ static int step_impl(const fv_config* cfg, void* U, double dt, const double* dt_
                      unsigned long long* inv_max = nullptr)
 {
     int r;
-    if ((r = stage_dispatch(cfg, 1, U, U, w.A, dt, dt_dev, st))) return r;
-    if ((r = stage_dispatch(cfg, 2, U, w.A, w.B, dt, dt_dev, st))) return r;
-    return stage_dispatch(cfg, 3, U, w.B, U, dt, dt_dev, st, inv_max);
+    if ((r = stage_dispatch(cfg, 1, U, U, w.A, dt, dt_dev, st, nullptr, &w))) return r;
+    if ((r = stage_dispatch(cfg, 2, U, w.A, w.B, dt, dt_dev, st, nullptr, &w))) return r;
+    return stage_dispatch(cfg, 3, U, w.B, U, dt, dt_dev, st, inv_max, &w);
 }
 
 int rk3_step(const fv_config* cfg, void* U, double dt, void* ws, void* stream)
@@ -439,6 +503,7 @@ static int adjoint_supported(const fv_config* cfg)
     if (cfg->dtype != FV_F64) return fail(FV_EUNSUPPORTED, "the adjoint is FP64");
     if (positivity_on(cfg)) return fail(FV_EUNSUPPORTED, "the adjoint needs the positivity limiters off");
     if (cfg->recon != 0) return fail(FV_EUNSUPPORTED, "the adjoint covers primitive-variable reconstruction");
+    if (cfg->scheme != 0) return fail(FV_EUNSUPPORTED, "the adjoint covers WENO5-Z reconstruction");
     return FV_OK;
 }
 
@@ -709,6 +774,9 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if ((r = check_ptr(U[i], "U")) || (r = check_ptr(ws[i], "ws"))) return fail(r, "member %d: %s", i, last_error());
         if (!(cfgs[i].cfl > 0)) return fail(FV_EINVAL, "member %d: cfl must be > 0", i);
         if (cfgs[i].recon != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use primitive reconstruction", i);
+        if (cfgs[i].scheme != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use WENO5-Z reconstruction", i);
+        if (visc6(&cfgs[i])) return fail(FV_EUNSUPPORTED, "member %d: batches use 4th-order viscous fluxes", i);
+        if (cfgs[i].thinc) return fail(FV_EUNSUPPORTED, "member %d: batches run without THINC", i);
         if (cfgs[i].visc_law != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use constant viscosity", i);
     }
     // groups in order of first appearance; members keep their order inside a group

@@ -48,6 +48,16 @@
 
 namespace fv {
 
+// Reconstruction variants of the stage kernel: WENO5-Z or TENO6-A (Sec. 3.2
+// step 3) of primitive or characteristic variables (value: recon + 2 scheme).
+enum { REC_WENO_PRIM = 0, REC_WENO_CHAR = 1, REC_TENO_PRIM = 2, REC_TENO_CHAR = 3 };
+// Viscous variants of the viscous model: constant viscosity, a viscosity law
+// (both 4th-order fluxes inside the stage), or sixth-order fluxes from the
+// separate passes of fv_visc6.hip (any law)
+enum { VM_CONST = 0, VM_LAW = 1, VM_EXT = 2 };
+// and of the five-equation model: THINC interface capturing off / on
+enum { XM_PLAIN = 0, XM_THINC = 1 };
+
 // Arguments of the fused stage kernel (passed by value).
 template <typename Real>
 struct StageArgs {
@@ -62,7 +72,7 @@ struct StageArgs {
     int bc[6];
     int tiles_x, tiles_y, zchunk, nchunks;
     int positivity, ndim;
-    int recon;           // 0: primitive variables, 1: characteristic variables
+    int recon;           // reconstruction variant REC_* (variables and scheme)
     Material<Real> mat;
     Tolerances<Real> tol;
     Real weno_eps;
@@ -75,6 +85,11 @@ struct StageArgs {
     double kvisc;        // (14/3) mu / dx_min^2 (0 without viscosity)
     double kvisc_h;      // (14/3) / dx_min^2 (viscosity laws)
     ViscLaw<Real> vl;    // viscosity law of the faces (law 0: mu and kappa above)
+    // sixth-order viscous fluxes computed by the separate passes of fv_visc6.hip:
+    // their divergence [4][ncell] (momentum x, y, z, energy), added when a cell is
+    // finalised; null: the stage computes the 4th-order viscous fluxes itself
+    const Real* rvisc;
+    int thinc;           // five-equation model: THINC volume-fraction faces in interface cells
 };
 
 struct LaunchGeom {
@@ -94,6 +109,27 @@ size_t stage_lds_bytes();
 template <typename Real>
 hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
                               hipStream_t st);
+
+// Sixth-order central viscous fluxes (fv_visc6.hip), three passes over the
+// state U of the viscous model:
+//   Q  [4][npad]  u, v, w, theta = p / rho on the box padded by 3 cells
+//                 (boundary conditions by index mapping);
+//   G  [9][npad]  du_c/dx_e at cell centres (index 3 c + e), where the
+//                 e-coordinate of the cell is interior;
+//   Rv [4][ncell] divergence of the viscous face fluxes (momentum x, y, z,
+//                 energy): R = -div(F^c - F^d) receives +div F^d.
+template <typename Real>
+struct Visc6Args {
+    int nx, ny, nz;
+    int bc[6];
+    long long ncell, npad;
+    Material<Real> mat;
+    ViscLaw<Real> vl;
+    Real ih[3];  // 1 / dx_d
+};
+
+template <typename Real>
+hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* G, Real* Rv, hipStream_t st);
 
 // Per-problem scalars of a batch in CFL mode.
 struct BatchScalars {

@@ -1,7 +1,8 @@
 // fv_physics.h -- point-wise device functions of the fused finite-volume stage
 // for gfx950: equation of state, primitive/conservative maps, WENO5-Z
 // reconstruction with smoothness indicators shared between the two faces of a
-// cell, the HLLC flux and the 4th-order central viscous flux.
+// cell, TENO6-A face reconstruction, characteristic projection, the HLLC flux
+// and the 4th-order central viscous flux.
 //
 // Notation follows arXiv:2402.05193: W primitive, U conservative (Sec. 2.1,
 // 2.3), stiffened gas and isobaric mixture closure (Sec. 2.4), WENO5-Z and
@@ -299,16 +300,127 @@ __device__ __forceinline__ Real weno5z_one(Real a, Real b, Real c, Real d, Real 
     return (g0 * p0 + m1 * p1 + m2 * p2) * rcp(Real(6) * (g0 + m1 + m2));
 }
 
-// Face states by WENO5-Z of characteristic variables (Sec. 3.2 steps 1-4 and
+// ---------------------------------------------------------------- TENO6-A
+// Six-point targeted ENO reconstruction with adaptive dissipation (Sec. 3.2
+// step 3; the candidate stencils are those of the reconstruction schematic:
+// S0 = {i-2,i-1,i}, S1 = {i-1,i,i+1}, S2 = {i,i+1,i+2}, S3 = {i,..,i+3}).
+// A face between cells i and i+1 reads v_{i-2..i+3} = a..f for both states.
+//
+// Cut-off C_T = 10^-floor(beta_bar), beta_bar = 10.5 - 3.5 (1 - g(m)),
+// g(m) = (1 - m)^4 (1 + 4 m), m = 1 - min(1, eta / 0.17), eta the smallest
+// cell indicator (|2 D- D+| + e) / (D-^2 + D+^2 + e) of cells i-1 .. i+2
+// (e = 0.9 * 0.17 * 1e-6 / (1 - 0.9 * 0.17)).  The indicator set is the same
+// for both face states.  All four indicators at or above 0.17 give m = 0 and
+// C_T = 1e-10 without a division.
+template <typename Real>
+__device__ __forceinline__ Real teno6a_cutoff(Real a, Real b, Real c, Real d, Real e, Real f)
+{
+    const Real cr = Real(0.17);
+    const Real ee = Real(0.9 * 0.17 / (1.0 - 0.9 * 0.17) * 1e-6);
+    const Real d0 = b - a, d1 = c - b, d2 = d - c, d3 = e - d, d4 = f - e;
+    const Real n0 = fabs(Real(2) * d0 * d1) + ee, q0 = fma(d0, d0, fma(d1, d1, ee));
+    const Real n1 = fabs(Real(2) * d1 * d2) + ee, q1 = fma(d1, d1, fma(d2, d2, ee));
+    const Real n2 = fabs(Real(2) * d2 * d3) + ee, q2 = fma(d2, d2, fma(d3, d3, ee));
+    const Real n3 = fabs(Real(2) * d3 * d4) + ee, q3 = fma(d3, d3, fma(d4, d4, ee));
+    if (n0 >= cr * q0 && n1 >= cr * q1 && n2 >= cr * q2 && n3 >= cr * q3) return Real(1e-10);
+    const Real eta = fmin(fmin(n0 * rcp(q0), n1 * rcp(q1)), fmin(n2 * rcp(q2), n3 * rcp(q3)));
+    const Real m = Real(1) - fmin(Real(1), eta * Real(1.0 / 0.17));
+    const Real om = Real(1) - m, om2 = om * om;
+    const Real g = om2 * om2 * fma(Real(4), m, Real(1));
+    const Real bbar = Real(10.5) - Real(3.5) * (Real(1) - g);
+    return bbar >= Real(10) ? Real(1e-10) : bbar >= Real(9) ? Real(1e-9) : bbar >= Real(8) ? Real(1e-8) : Real(1e-7);
+}
+
+// Left-biased TENO6-A value at x_{i+1/2} from v_{i-2..i+3} = a..f (the right
+// state of the face is the same function of the mirrored stencil).
+//  * Jiang-Shu smoothness indicators beta_0..beta_3 of the candidates and
+//    beta_6 of the six-cell polynomial, over cell i; the 4- and 6-cell ones
+//    are written with values relative to v_i (they see differences only), so
+//    their rounding scales with the data's variation, not its magnitude.
+//  * tau_6 = |beta_6 - (beta_0 + 4 beta_1 + beta_2) / 6|.
+//  * stencil k is dropped when gamma_k / sum gamma < C_T, gamma_k =
+//    (1 + tau_6 / (beta_k + eps))^6; evaluated as s_k^6 < C_T sum s^6 with
+//    s_k = gamma_k^(1/6) / max gamma^(1/6) = A + A tau_6 / (beta_k + eps),
+//    A = e_min / (e_min + tau_6), which stays finite where gamma overflows.
+//  * kept stencils combine with the linear weights (1, 9, 6, 4) / 20.
+template <typename Real>
+__device__ __forceinline__ Real teno6a_one(Real a, Real b, Real c, Real d, Real e, Real f, Real eps, Real ct)
+{
+    const Real k13 = Real(13.0 / 12.0), q = Real(0.25);
+    const Real t0 = a - Real(2) * b + c, s0 = a - Real(4) * b + Real(3) * c;
+    const Real t1 = b - Real(2) * c + d, s1 = b - d;
+    const Real t2 = c - Real(2) * d + e, s2 = Real(3) * c - Real(4) * d + e;
+    const Real b0 = k13 * t0 * t0 + q * s0 * s0;
+    const Real b1 = k13 * t1 * t1 + q * s1 * s1;
+    const Real b2 = k13 * t2 * t2 + q * s2 * s2;
+    const Real A = a - c, B = b - c, D = d - c, E = e - c, F = f - c;
+    const Real b3 = (D * (Real(11003) * D - Real(17246) * E + Real(4642) * F) + E * (Real(7043) * E - Real(3882) * F) +
+                     Real(547) * F * F) *
+                    Real(1.0 / 240.0);
+    const Real b6 = (A * (Real(271779) * A - Real(2380800) * B - Real(3462252) * D + Real(1458762) * E -
+                          Real(245620) * F) +
+                     B * (Real(5653317) * B + Real(17905032) * D - Real(7727988) * E + Real(1325006) * F) +
+                     D * (Real(17195652) * D - Real(15880404) * E + Real(2863984) * F) +
+                     E * (Real(3824847) * E - Real(1429976) * F) + Real(139633) * F * F) *
+                    Real(1.0 / 120960.0);
+    const Real tau = fabs(b6 - (b0 + Real(4) * b1 + b2) * Real(1.0 / 6.0));
+    const Real e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b3 + eps;
+    Real r0, r1, r2, r3;
+    if constexpr (sizeof(Real) == 8) {
+        const Real p01 = e0 * e1, p23 = e2 * e3;
+        const Real R = rcp(p01 * p23);
+        const Real u = p23 * R, v = p01 * R;
+        r0 = e1 * u;
+        r1 = e0 * u;
+        r2 = e3 * v;
+        r3 = e2 * v;
+    } else {
+        r0 = rcp(e0);
+        r1 = rcp(e1);
+        r2 = rcp(e2);
+        r3 = rcp(e3);
+    }
+    const Real em = fmin(fmin(e0, e1), fmin(e2, e3));
+    const Real An = em * rcp(em + tau), Bn = An * tau;
+    auto pow6 = [](Real x) {
+        const Real x2 = x * x;
+        return x2 * x2 * x2;
+    };
+    const Real g0 = pow6(fma(Bn, r0, An)), g1 = pow6(fma(Bn, r1, An));
+    const Real g2 = pow6(fma(Bn, r2, An)), g3 = pow6(fma(Bn, r3, An));
+    const Real thr = ct * (g0 + g1 + g2 + g3);
+    const Real w0 = g0 >= thr ? Real(1) : Real(0), w1 = g1 >= thr ? Real(9) : Real(0);
+    const Real w2 = g2 >= thr ? Real(6) : Real(0), w3 = g3 >= thr ? Real(4) : Real(0);
+    // candidates: 6 p_0..2 and 12 p_3
+    const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
+    const Real p1 = -b + Real(5) * c + Real(2) * d;
+    const Real p2 = Real(2) * c + Real(5) * d - e;
+    const Real p3 = Real(3) * c + Real(13) * d - Real(5) * e + f;
+    const Real num = Real(2) * (w0 * p0 + w1 * p1 + w2 * p2) + w3 * p3;
+    return num * rcp(Real(12) * (w0 + w1 + w2 + w3));
+}
+
+// Both TENO6-A states of the face between cells i and i+1 from v_{i-2..i+3}.
+template <typename Real>
+__device__ __forceinline__ void teno6a_pair(Real a, Real b, Real c, Real d, Real e, Real f, Real eps, Real& vl,
+                                            Real& vr)
+{
+    const Real ct = teno6a_cutoff(a, b, c, d, e, f);
+    vl = teno6a_one(a, b, c, d, e, f, eps, ct);
+    vr = teno6a_one(f, e, d, c, b, a, eps, ct);
+}
+
+// Face states by WENO5-Z or TENO6-A of characteristic variables (Sec. 3.2 steps 1-4 and
 // the appendix eigenvectors).  st(s, m): component m of W at stencil slot s,
 // slots 0..5 = cells f-3 .. f+2 around the face between cells f-1 and f.  The
 // frozen face state is the mean of cells f-1 and f.  With rho c the acoustic
-// impedance and rho c^2 taken there, the projection K^{-1} W, scaled per
-// field, gives the acoustic variables p -/+ (rho c) u_n, the densities minus
+// impedance and rho c^2 taken there, the projection K^{-1} W gives the
+// acoustic variables (p -/+ (rho c) u_n) / (2 rho c^2), the densities minus
 // their acoustic part (rho_k - (rho_k / (rho c^2)) p), and the tangential
 // velocities and the volume fraction unchanged; each is reconstructed from both
-// sides and mapped back with K.
-template <typename Real, int MODEL, int DIR, typename Stencil>
+// sides and mapped back with K.  (WENO5-Z does not see a per-field scale;
+// TENO6-A's cut-off does, so the variables are K^{-1} W exactly.)
+template <typename Real, int MODEL, int DIR, bool TENO, typename Stencil>
 __device__ __forceinline__ void char_face_states(const Material<Real>& mat, Stencil st, Real eps, Real* wl, Real* wr)
 {
     constexpr int NC = Layout<MODEL>::NC, V = Layout<MODEL>::V, P = Layout<MODEL>::P;
@@ -320,7 +432,8 @@ __device__ __forceinline__ void char_face_states(const Material<Real>& mat, Sten
     const Real rc2 = rhoc2<Real, MODEL>(mat, wf);
     const Real irc2 = rcp(rc2);
     const Real z = sqrt_fast(density<Real, MODEL>(wf) * rc2);  // rho c
-    const Real iz2 = Real(0.5) * rcp(z);
+    const Real hh = Real(0.5) * irc2, zh = z * hh;             // 1/(2 rho c^2), 1/(2 c)
+    const Real cs = rc2 * rcp(z);                              // c
     Real g[ND];
 #pragma unroll
     for (int k = 0; k < ND; k++) g[k] = wf[k] * irc2;
@@ -328,17 +441,21 @@ __device__ __forceinline__ void char_face_states(const Material<Real>& mat, Sten
         Real q[6];
 #pragma unroll
         for (int s = 0; s < 6; s++) q[s] = field(s);
-        L = weno5z_one(q[0], q[1], q[2], q[3], q[4], eps);
-        R = weno5z_one(q[5], q[4], q[3], q[2], q[1], eps);
+        if constexpr (TENO) {
+            teno6a_pair(q[0], q[1], q[2], q[3], q[4], q[5], eps, L, R);
+        } else {
+            L = weno5z_one(q[0], q[1], q[2], q[3], q[4], eps);
+            R = weno5z_one(q[5], q[4], q[3], q[2], q[1], eps);
+        }
     };
     Real amL, amR, apL, apR;
-    both([&](int s) { return st(s, P) - z * st(s, UN); }, amL, amR);
-    both([&](int s) { return st(s, P) + z * st(s, UN); }, apL, apR);
-    const Real pL = Real(0.5) * (amL + apL), pR = Real(0.5) * (amR + apR);
+    both([&](int s) { return fma(-zh, st(s, UN), hh * st(s, P)); }, amL, amR);
+    both([&](int s) { return fma(zh, st(s, UN), hh * st(s, P)); }, apL, apR);
+    const Real pL = rc2 * (amL + apL), pR = rc2 * (amR + apR);
     wl[P] = pL;
     wr[P] = pR;
-    wl[UN] = (apL - amL) * iz2;
-    wr[UN] = (apR - amR) * iz2;
+    wl[UN] = (apL - amL) * cs;
+    wr[UN] = (apR - amR) * cs;
 #pragma unroll
     for (int k = 0; k < ND; k++) {
         Real eL, eR;
@@ -349,6 +466,48 @@ __device__ __forceinline__ void char_face_states(const Material<Real>& mat, Sten
     both([&](int s) { return st(s, T1); }, wl[T1], wr[T1]);
     both([&](int s) { return st(s, T2); }, wl[T2], wr[T2]);
     if constexpr (MODEL == DIM) both([&](int s) { return st(s, 6); }, wl[6], wr[6]);
+}
+
+// ---------------------------------------------------------------- THINC
+// Interface capturing of the five-equation model (Sec. 3.2, after the
+// reconstruction).  A cell is an interface cell when eps <= a0 <= 1 - eps
+// (eps = 1e-4) and the volume fraction is monotone through it along the face
+// normal (am, a0, ap).  Its profile over the cell, xt in [0, 1] from its -d
+// face, is (1 + theta tanh(beta (xt + x_c))) / 2 with theta = sgn(ap - am),
+// beta = |n_d| + 0.01 (n = grad alpha / |grad alpha|; g_d and gn2 = |grad|^2 in
+// any common scale) and x_c such that the profile's mean is a0:
+//   T = tanh(beta x_c) = (exp(theta beta (2 a0 - 1)) - cosh beta) / sinh beta.
+// Face values: (1 + theta T) / 2 at the -d face (side 0) and
+// (1 + theta tanh(beta + beta x_c)) / 2 at the +d face (side 1), the latter
+// from the addition theorem.  Returns false (af untouched) outside interface cells.
+template <typename Real>
+__device__ __forceinline__ bool thinc_face(Real am, Real a0, Real ap, Real gd, Real gn2, int side, Real& af)
+{
+    if (!(a0 >= Real(1e-4) && a0 <= Real(1) - Real(1e-4) && (ap - a0) * (a0 - am) > Real(0))) return false;
+    const Real theta = ap > am ? Real(1) : Real(-1);
+    const Real beta = fabs(gd) * rsqrt(gn2) + Real(0.01);
+    const Real eb = exp(beta), ieb = rcp(eb);
+    const Real ch = Real(0.5) * (eb + ieb), sh = Real(0.5) * (eb - ieb);
+    const Real Q = exp(theta * beta * (Real(2) * a0 - Real(1)));
+    const Real T = (Q - ch) * rcp(sh);
+    Real t = T;
+    if (side) {
+        const Real tb = sh * rcp(ch);
+        t = (tb + T) * rcp(Real(1) + tb * T);
+    }
+    af = Real(0.5) * (Real(1) + theta * t);
+    return true;
+}
+
+// THINC face state of a cell (five-equation layout): volume fraction af and the
+// partial densities from the cell's phase densities rho_k = (alpha_k rho_k) / alpha_k;
+// velocity and pressure keep the reconstructed values.
+template <typename Real>
+__device__ __forceinline__ void thinc_state(Real af, Real ar1, Real ar2, Real a0, Real* w)
+{
+    w[6] = af;
+    w[0] = af * (ar1 * rcp(a0));
+    w[1] = (Real(1) - af) * (ar2 * rcp(Real(1) - a0));
 }
 
 // ---------------------------------------------------------------- HLLC

@@ -95,10 +95,11 @@ __device__ __forceinline__ double inverse_dt(const StageArgs<Real>& a, const Rea
 
 // LDS geometry of one tile of BX x BY cells worked on by NTH threads
 // (NTH >= BX * BY; the x/y task lists are sized to fit NTH in one round)
-template <typename Real, int MODEL, int BX, int BY, int NTH>
+template <typename Real, int MODEL, int BX, int BY, int NTH, bool VISC_ = (MODEL == NS), bool THINC_ = false>
 struct Tile {
     static constexpr int NC = Layout<MODEL>::NC;
-    static constexpr bool VISC = MODEL == NS;
+    static constexpr bool VISC = VISC_;  // the stage computes viscous fluxes itself
+    static constexpr bool THINC = THINC_;  // interface capturing (five-equation model)
     static constexpr int NT = NTH;
     static constexpr int NCELL = BX * BY;
     static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho) of the LDS plane
@@ -111,23 +112,30 @@ struct Tile {
     static constexpr int RX = (BX + 4) * BY, RY = BX * (BY + 4);  // viscous cell regions
     static constexpr int DZ_SIZE = VISC ? 2 * RX + 2 * RY : 0;    // d/dz of (u,w) on RX, (v,w) on RY
     static constexpr int DT_SIZE = VISC ? 2 * (RX > RY ? RX : RY) : 0;  // in-plane tangential d/dx_t
-    static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : 0);
+    // halo ring of the plane; corners: 2 deep for the viscous cross terms, 1 deep
+    // for the volume-fraction gradient of THINC
+    static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : (THINC ? 4 : 0));
+    // THINC: d(alpha)/dz at the plane for the tile and its 1-cell ring
+    static constexpr int AZ_SIZE = THINC ? (BX + 2) * (BY + 2) : 0;
+    static constexpr int NRING = 2 * BX + 2 * BY + 4;
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
     // five-equation model keeps them in registers instead (LDS budget)
     static constexpr bool ACC_LDS = MODEL != DIM;
     static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : 0;
     static constexpr size_t bytes()
     {
-        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE);
+        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE + AZ_SIZE);
     }
 };
 
 // One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
-template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
 __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
 {
     using L = Layout<MODEL>;
-    using TL = Tile<Real, MODEL, BX, BY, NTH>;
+    constexpr bool THINC = MODEL == DIM && VMODE == XM_THINC;
+    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT, THINC>;
+    constexpr bool VLAW = MODEL == NS && VMODE == VM_LAW;
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
     constexpr bool ACC_LDS = TL::ACC_LDS;
@@ -144,6 +152,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
     Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
     Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NCELL]  x/y partial sums of R
+    Real* AZ = ACC + TL::ACC_SIZE;  // [BY+2][BX+2]    THINC: d(alpha)/dz, tile and 1-cell ring
 
     const Material<Real> mat = a.mat;
     const Tolerances<Real> tol = a.tol;
@@ -193,7 +202,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     // register window W(s-3 .. s+2) of the own column
     constexpr int NWIN = FACE ? 7 : 6, WO = FACE ? 1 : 0;  // face tasks need s-4 .. s+2
     Real win[NWIN][NC];
-    const int s_begin = VISC ? z0 - 2 : z0;
+    // viscous: two warm-up planes for the in-plane derivatives of the first z faces;
+    // THINC: one, for the in-plane volume-fraction gradient of cell z0-1
+    const int s_begin = VISC ? z0 - 2 : (THINC ? z0 - 1 : z0);
 #pragma unroll
     for (int q = 0; q < NWIN - 1; q++) {
         if (has_cell) load_w(gx, gy, s_begin - 3 - WO + q, win[q]);
@@ -208,6 +219,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
     Real uhzl = 0;            // its upwinded normal velocity (DIM)
     Real Dc[3][4];            // NS: (dw/dx, du/dx, dw/dy, dv/dy) at planes s-3, s-2, s-1
+    Real Ag[2][2] = {{0, 0}, {0, 0}};  // THINC: (d alpha/dx, d alpha/dy) of the own column at planes s-2, s-1
 #pragma unroll
     for (int m = 0; m < NC; m++) {
         vminus[m] = 0;
@@ -235,10 +247,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             for (int f = 0; f < NC; f++) raw[f] = Real(1);
         if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
         const bool xy = (s >= z0) && (s < z1);
-        const bool need_plane = xy || (VISC && s >= z0 - 2);
+        // THINC also stages plane z1 (the cell above the last z face of the chunk)
+        const bool need_plane = xy || (VISC && s >= z0 - 2) || (THINC && s >= z0 - 1 && s <= z1);
         Real accC[NC];
         Real srcC = 0;
         Real Dnew[4] = {0, 0, 0, 0};
+        Real Anew[2] = {0, 0};
 #pragma unroll
         for (int m = 0; m < NC; m++) accC[m] = 0;
 
@@ -271,11 +285,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     hi = hh % BX;
                     const int k = hh / BX;
                     hj = k < 3 ? k - 3 : BY + k - 3;
-                } else {
+                } else if constexpr (VISC) {
                     const int hh = h - 6 * BY - 6 * BX;  // 2-deep corners (viscous cross terms)
                     const int ci = hh & 3, cj = hh >> 2;
                     hi = ci < 2 ? ci - 2 : BX + ci - 2;
                     hj = cj < 2 ? cj - 2 : BY + cj - 2;
+                } else {
+                    const int hh = h - 6 * BY - 6 * BX;  // 1-deep corners (THINC gradient)
+                    hi = (hh & 1) ? BX : -1;
+                    hj = (hh & 2) ? BY : -1;
                 }
                 if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
             }
@@ -288,6 +306,37 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
             if (has_cell) stage_w(tx, ty, win[3 + WO]);
+            if constexpr (THINC) {
+                // d(alpha)/dz at plane s (second-order central): own column from the
+                // window, the 1-cell ring from memory (highest-numbered threads)
+                const Real hz = Real(0.5) * idz;
+                if (has_cell) AZ[(ty + 1) * (BX + 2) + tx + 1] = (win[4 + WO][6] - win[2 + WO][6]) * hz;
+                const int h = NT - 1 - tid;
+                if (h < TL::NRING) {
+                    int i, j;
+                    if (h < 2 * BY) {
+                        j = h >> 1;
+                        i = (h & 1) ? BX : -1;
+                    } else if (h < 2 * BY + 2 * BX) {
+                        const int hh = h - 2 * BY;
+                        i = hh >> 1;
+                        j = (hh & 1) ? BY : -1;
+                    } else {
+                        const int hh = h - 2 * BY - 2 * BX;
+                        i = (hh & 1) ? BX : -1;
+                        j = (hh & 2) ? BY : -1;
+                    }
+                    bool fx = false, fy = false, fz = false;
+                    const int ii = map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
+                    const int jj = map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
+                    const int km = map_index(s - 1, a.nz, a.bc[4], a.bc[5], fz);
+                    const int kp = map_index(s + 1, a.nz, a.bc[4], a.bc[5], fz);
+                    const long long col = (long long)jj * a.nx + ii, plane = (long long)a.ny * a.nx;
+                    const Real am = a.Uk[6 * a.ncell + km * plane + col];
+                    const Real ap = a.Uk[6 * a.ncell + kp * plane + col];
+                    AZ[(j + 1) * (BX + 2) + i + 1] = (ap - am) * hz;
+                }
+            }
             if (has_halo) {
                 Real w[NC];
                 cons_to_prim<Real, MODEL>(mat, hu, w);
@@ -358,6 +407,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Dnew[2] = dcell(wp(V + 2, tx, ty - 2), wp(V + 2, tx, ty - 1), wp(V + 2, tx, ty + 1), wp(V + 2, tx, ty + 2), i12y);
                 Dnew[3] = dcell(wp(V + 1, tx, ty - 2), wp(V + 1, tx, ty - 1), wp(V + 1, tx, ty + 1), wp(V + 1, tx, ty + 2), i12y);
             }
+            if (THINC && has_cell) {
+                // in-plane volume-fraction gradient of the own column (THINC at the z faces)
+                Anew[0] = (wp(6, tx + 1, ty) - wp(6, tx - 1, ty)) * (Real(0.5) * idx);
+                Anew[1] = (wp(6, tx, ty + 1) - wp(6, tx, ty - 1)) * (Real(0.5) * idy);
+            }
         }
 
         if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
@@ -415,6 +469,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         wr[m] = vp[m];
                     }
                 }
+                if constexpr (THINC) {
+                    // interface cells s-2 (its +z face) and s-1 (its -z face)
+                    const Real hz = Real(0.5) * idz;
+                    const Real a0 = win[WO][6], a1 = win[1 + WO][6], a2 = win[2 + WO][6], a3 = win[3 + WO][6];
+                    Real af, gz = (a2 - a0) * hz;
+                    if (thinc_face(a0, a1, a2, gz, Ag[0][0] * Ag[0][0] + Ag[0][1] * Ag[0][1] + gz * gz, 1, af))
+                        thinc_state(af, win[1 + WO][0], win[1 + WO][1], a1, wl);
+                    gz = (a3 - a1) * hz;
+                    if (thinc_face(a1, a2, a3, gz, Ag[1][0] * Ag[1][0] + Ag[1][1] * Ag[1][1] + gz * gz, 0, af))
+                        thinc_state(af, win[2 + WO][0], win[2 + WO][1], a2, wr);
+                }
                 if constexpr (POS) {
                     if (inadmissible_w<Real, MODEL>(mat, tol, wl))
 #pragma unroll
@@ -447,6 +512,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
                     }
                     if constexpr (MODEL == DIM) r[6] += win[1 + WO][6] * (srcA + (uh - uhzl) * idz);
+                    if constexpr (MODEL == NS && VMODE == VM_EXT) {
+                        // divergence of the sixth-order viscous fluxes (separate passes)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) r[V + c] += a.rvisc[c * a.ncell + q];
+                        r[P] += a.rvisc[3 * a.ncell + q];
+                    }
                     Real unew[NC];
                     if (!FV_PREFETCH_RK && a.mode != 0) {
 #pragma unroll
@@ -456,7 +527,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         }
                     }
                     store_cell_impl<Real, NC>(a, q, r, dt, pre_k, pre_n, unew);
-                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, VLAW>(a, unew));
+                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, VMODE != VM_CONST>(a, unew));
                 }
 #pragma unroll
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
@@ -539,6 +610,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 for (int m = 0; m < NC; m++) {
                     wl[m] = FL[m * TL::NFX + t];
                     wr[m] = FR[m * TL::NFX + t];
+                }
+                if constexpr (THINC) {
+                    // interface cells f-1 (its +x face) and f (its -x face)
+                    const Real hx = Real(0.5) * idx, hy = Real(0.5) * idy;
+                    const Real am = wp(6, f - 2, j), a0 = wp(6, f - 1, j), a1 = wp(6, f, j), ap = wp(6, f + 1, j);
+                    Real af, gx = (a1 - am) * hx;
+                    Real gy = (wp(6, f - 1, j + 1) - wp(6, f - 1, j - 1)) * hy, gz = AZ[(j + 1) * (BX + 2) + f];
+                    if (thinc_face(am, a0, a1, gx, gx * gx + gy * gy + gz * gz, 1, af))
+                        thinc_state(af, wp(0, f - 1, j), wp(1, f - 1, j), a0, wl);
+                    gx = (ap - a0) * hx;
+                    gy = (wp(6, f, j + 1) - wp(6, f, j - 1)) * hy;
+                    gz = AZ[(j + 1) * (BX + 2) + f + 1];
+                    if (thinc_face(a0, a1, ap, gx, gx * gx + gy * gy + gz * gz, 0, af))
+                        thinc_state(af, wp(0, f, j), wp(1, f, j), a1, wr);
                 }
                 if constexpr (POS) {
                     Real wi[NC], wj[NC];
@@ -661,6 +746,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     wl[m] = GL[m * TL::NFY + t];
                     wr[m] = GR[m * TL::NFY + t];
                 }
+                if constexpr (THINC) {
+                    // interface cells of rows f-1 (its +y face) and f (its -y face)
+                    const Real hx = Real(0.5) * idx, hy = Real(0.5) * idy;
+                    const Real am = wp(6, i, f - 2), a0 = wp(6, i, f - 1), a1 = wp(6, i, f), ap = wp(6, i, f + 1);
+                    Real af, gy = (a1 - am) * hy;
+                    Real gx = (wp(6, i + 1, f - 1) - wp(6, i - 1, f - 1)) * hx, gz = AZ[f * (BX + 2) + i + 1];
+                    if (thinc_face(am, a0, a1, gy, gx * gx + gy * gy + gz * gz, 1, af))
+                        thinc_state(af, wp(0, i, f - 1), wp(1, i, f - 1), a0, wl);
+                    gy = (ap - a0) * hy;
+                    gx = (wp(6, i + 1, f) - wp(6, i - 1, f)) * hx;
+                    gz = AZ[(f + 1) * (BX + 2) + i + 1];
+                    if (thinc_face(a0, a1, ap, gy, gx * gx + gy * gy + gz * gz, 0, af))
+                        thinc_state(af, wp(0, i, f), wp(1, i, f), a1, wr);
+                }
                 if constexpr (POS) {
                     Real wi[NC], wj[NC];
 #pragma unroll
@@ -731,6 +830,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Dc[2][c] = Dnew[c];
             }
         }
+        if constexpr (THINC) {
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                Ag[0][c] = Ag[1][c];
+                Ag[1][c] = Anew[c];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < NWIN - 1; q++)
 #pragma unroll
@@ -752,16 +858,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 }
 
-template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 #if FV_KERNARG_INPLACE
     // the argument block read in place from the kernel-argument segment
     const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
-    stage_body<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
 #else
-    stage_body<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
+    stage_body<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
 #endif
 }
 
@@ -781,42 +887,42 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU)
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stage_body<Real, MODEL, POS, REC_WENO_PRIM, false, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+    stage_body<Real, MODEL, POS, REC_WENO_PRIM, VM_CONST, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, bool POS, int REC, bool VLAW, int BX, int BY, int NTH>
+template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    using TL = Tile<Real, MODEL, BX, BY, NTH>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT, MODEL == DIM && VMODE == XM_THINC>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>,
+        hipError_t e = hipFuncSetAttribute((const void*)stage_kernel<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, REC, VLAW, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds,
+    hipLaunchKernelGGL((stage_kernel<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>), dim3(g.nblocks), dim3(NTH), lds,
                        st, args);
     return hipGetLastError();
 }
 
-template <typename Real, int MODEL, int REC, bool VLAW>
+template <typename Real, int MODEL, int REC, int VMODE>
 static hipError_t launch_pos(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    if (args.positivity) return launch_tile<Real, MODEL, true, REC, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
-    return launch_tile<Real, MODEL, false, REC, VLAW, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    if (args.positivity) return launch_tile<Real, MODEL, true, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    return launch_tile<Real, MODEL, false, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
-template <typename Real, int MODEL, bool VLAW>
+template <typename Real, int MODEL, int VMODE>
 static hipError_t launch_variant(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     switch (args.recon) {
-    case REC_WENO_CHAR: return launch_pos<Real, MODEL, REC_WENO_CHAR, VLAW>(args, g, st);
-    case REC_TENO_PRIM: return launch_pos<Real, MODEL, REC_TENO_PRIM, VLAW>(args, g, st);
-    case REC_TENO_CHAR: return launch_pos<Real, MODEL, REC_TENO_CHAR, VLAW>(args, g, st);
-    default: return launch_pos<Real, MODEL, REC_WENO_PRIM, VLAW>(args, g, st);
+    case REC_WENO_CHAR: return launch_pos<Real, MODEL, REC_WENO_CHAR, VMODE>(args, g, st);
+    case REC_TENO_PRIM: return launch_pos<Real, MODEL, REC_TENO_PRIM, VMODE>(args, g, st);
+    case REC_TENO_CHAR: return launch_pos<Real, MODEL, REC_TENO_CHAR, VMODE>(args, g, st);
+    default: return launch_pos<Real, MODEL, REC_WENO_PRIM, VMODE>(args, g, st);
     }
 }
 
@@ -831,11 +937,16 @@ template <typename Real, int MODEL>
 hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     // a viscosity law is a separate instantiation (viscous model only): the law's
-    // pow() must not weigh on the constant-viscosity kernel
+    // pow() must not weigh on the constant-viscosity kernel; sixth-order viscous
+    // fluxes come from separate passes (the stage adds them)
     if constexpr (MODEL == NS) {
-        if (args.vl.law != 0) return launch_variant<Real, MODEL, true>(args, g, st);
+        if (args.rvisc) return launch_variant<Real, MODEL, VM_EXT>(args, g, st);
+        if (args.vl.law != 0) return launch_variant<Real, MODEL, VM_LAW>(args, g, st);
     }
-    return launch_variant<Real, MODEL, false>(args, g, st);
+    if constexpr (MODEL == DIM) {
+        if (args.thinc) return launch_variant<Real, MODEL, XM_THINC>(args, g, st);
+    }
+    return launch_variant<Real, MODEL, VM_CONST>(args, g, st);
 }
 
 template <typename Real, int MODEL, bool POS>

@@ -1,0 +1,24 @@
+// fv_stage_launch.hip -- dispatch of the stage kernels by model and the
+// batched (many-problem) stage kernels.
+#include "fv_stage.h"
+
+namespace fv {
+
+// the kernel families live in fv_stage_inst.hip objects
+#define FV_EXTERN_MODEL(R, M) \
+    extern template hipError_t launch_model<R, M>(const StageArgs<R>&, const LaunchGeom&, hipStream_t);
+FV_EXTERN_MODEL(double, EULER)
+FV_EXTERN_MODEL(double, NS)
+FV_EXTERN_MODEL(double, DIM)
+FV_EXTERN_MODEL(float, EULER)
+FV_EXTERN_MODEL(float, NS)
+FV_EXTERN_MODEL(float, DIM)
+#undef FV_EXTERN_MODEL
+
+template hipError_t launch_batch_stage<double>(int, bool, const StageArgs<double>*, const int*, int, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(int, bool, const StageArgs<float>*, const int*, int, int, hipStream_t);
+
+template hipError_t launch_stage<double>(int, const StageArgs<double>&, const LaunchGeom&, hipStream_t);
+template hipError_t launch_stage<float>(int, const StageArgs<float>&, const LaunchGeom&, hipStream_t);
+
+}  // namespace fv

@@ -1,0 +1,189 @@
+// fv_visc6.hip -- sixth-order central viscous fluxes for gfx950 (Sec. 2.1
+// dissipative fluxes; the single-phase simulations of the paper use 6th-order
+// central stencils for them).
+//
+// The fused stage kernel marches in z with the tangential derivatives of a z
+// face one plane behind; sixth-order face interpolation would need them two
+// planes ahead.  Instead the viscous part runs as three passes whose result
+// the stage adds when it finalises a cell:
+//   1. q = (u, v, w, theta = p/rho) on the box padded by 3 cells, boundary
+//      conditions by index mapping (the normal velocity negated across
+//      symmetry planes), one thread per padded cell;
+//   2. the velocity gradient du_c/dx_e at cell centres,
+//      (45 (q+1 - q-1) - 9 (q+2 - q-2) + (q+3 - q-3)) / (60 h), for every
+//      padded cell whose e-coordinate is interior (the only ones read);
+//   3. per interior cell and direction d, the fluxes of its two d-faces from
+//      the six cells across each face: face values
+//      (3 q-2 - 25 q-1 + 150 q0 + 150 q1 - 25 q2 + 3 q3) / 256, normal
+//      derivatives (2250 (q1 - q0) - 125 (q2 - q-1) + 9 (q3 - q-2)) / (1920 h),
+//      tangential derivatives interpolated from the gradients of pass 2; the
+//      stress tensor with the viscosity of the face temperature, the heat flux
+//      with the constant-Prandtl conductivity; then their divergence.
+// Passes 2 and 3 read neighbours along one axis at a time from contiguous
+// arrays (x fastest); the L1/L2 caches serve the reuse.
+#include <hip/hip_runtime.h>
+
+#include "fv_kernels.h"
+#include "fv_physics.h"
+
+namespace fv {
+namespace {
+
+template <typename Real>
+__device__ __forceinline__ Real ifc6(const Real* q)
+{
+    return (Real(150) * (q[2] + q[3]) - Real(25) * (q[1] + q[4]) + Real(3) * (q[0] + q[5])) * Real(1.0 / 256.0);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real dface6(const Real* q, Real ih)
+{
+    return (Real(2250) * (q[3] - q[2]) - Real(125) * (q[4] - q[1]) + Real(9) * (q[5] - q[0])) *
+           (ih * Real(1.0 / 1920.0));
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) visc6_q_kernel(const Visc6Args<Real> a, const Real* __restrict__ U,
+                                                      Real* __restrict__ Q)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.npad) return;
+    const int px = a.nx + 6, py = a.ny + 6;
+    const int i = (int)(t % px) - 3;
+    const long long r = t / px;
+    const int j = (int)(r % py) - 3, k = (int)(r / py) - 3;
+    bool fx = false, fy = false, fz = false;
+    const int ii = map_index(i, a.nx, a.bc[0], a.bc[1], fx);
+    const int jj = map_index(j, a.ny, a.bc[2], a.bc[3], fy);
+    const int kk = map_index(k, a.nz, a.bc[4], a.bc[5], fz);
+    const long long q = ((long long)kk * a.ny + jj) * a.nx + ii;
+    Real u[5], w[5];
+#pragma unroll
+    for (int m = 0; m < 5; m++) u[m] = U[m * a.ncell + q];
+    if (fx) u[1] = -u[1];
+    if (fy) u[2] = -u[2];
+    if (fz) u[3] = -u[3];
+    cons_to_prim<Real, NS>(a.mat, u, w);
+    Q[t] = w[1];
+    Q[a.npad + t] = w[2];
+    Q[2 * a.npad + t] = w[3];
+    Q[3 * a.npad + t] = w[4] * rcp(w[0]);
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) visc6_grad_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+                                                         Real* __restrict__ G)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.npad) return;
+    const int px = a.nx + 6, py = a.ny + 6;
+    const int i = (int)(t % px) - 3;
+    const long long r = t / px;
+    const int j = (int)(r % py) - 3, k = (int)(r / py) - 3;
+    const int c3[3] = {i, j, k}, n3[3] = {a.nx, a.ny, a.nz};
+    const long long s3[3] = {1, px, (long long)px * py};
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        if (c3[e] < 0 || c3[e] >= n3[e]) continue;
+        const long long s = s3[e];
+        const Real f = a.ih[e] * Real(1.0 / 60.0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const Real* q = Q + c * a.npad + t;
+            G[(3 * c + e) * a.npad + t] =
+                (Real(45) * (q[s] - q[-s]) - Real(9) * (q[2 * s] - q[-2 * s]) + (q[3 * s] - q[-3 * s])) * f;
+        }
+    }
+}
+
+// viscous flux (tau_x, tau_y, tau_z, u . tau + kappa dtheta/dn) of the d-face whose
+// six cells across are q[*][b .. b+5] and g*[b .. b+5]
+template <typename Real, int D>
+__device__ __forceinline__ void face6(const Visc6Args<Real>& a, const Real (*q)[7], const Real* gde1, const Real* gde2,
+                                      const Real* ge1, const Real* ge2, int b, Real* F)
+{
+    constexpr int E1 = (D + 1) % 3, E2 = (D + 2) % 3;
+    Real vf[3], dn[4];
+#pragma unroll
+    for (int c = 0; c < 3; c++) vf[c] = ifc6(q[c] + b);
+#pragma unroll
+    for (int c = 0; c < 4; c++) dn[c] = dface6(q[c] + b, a.ih[D]);
+    const Real thf = ifc6(q[3] + b);
+    const Real t_de1 = ifc6(gde1 + b), t_de2 = ifc6(gde2 + b);
+    const Real div = dn[D] + ifc6(ge1 + b) + ifc6(ge2 + b);
+    const Real mu = visc_mu(a.vl, thf);
+    const Real kap = mu * a.vl.kfac;
+    Real tau[3];
+    tau[D] = mu * (Real(2) * dn[D] - Real(2.0 / 3.0) * div);
+    tau[E1] = mu * (t_de1 + dn[E1]);
+    tau[E2] = mu * (t_de2 + dn[E2]);
+    F[0] = tau[0];
+    F[1] = tau[1];
+    F[2] = tau[2];
+    F[3] = vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2] + kap * dn[3];
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void direction6(const Visc6Args<Real>& a, const Real* __restrict__ Q,
+                                           const Real* __restrict__ G, long long tp, long long s, Real* acc)
+{
+    constexpr int E1 = (D + 1) % 3, E2 = (D + 2) % 3;
+    Real q[4][7], gde1[7], gde2[7], ge1[7], ge2[7];
+#pragma unroll
+    for (int o = 0; o < 7; o++) {
+        const long long x = tp + (o - 3) * s;
+#pragma unroll
+        for (int c = 0; c < 4; c++) q[c][o] = Q[c * a.npad + x];
+        gde1[o] = G[(3 * D + E1) * a.npad + x];
+        gde2[o] = G[(3 * D + E2) * a.npad + x];
+        ge1[o] = G[(3 * E1 + E1) * a.npad + x];
+        ge2[o] = G[(3 * E2 + E2) * a.npad + x];
+    }
+    Real Fl[4], Fu[4];
+    face6<Real, D>(a, q, gde1, gde2, ge1, ge2, 0, Fl);  // face between cells -1 and 0
+    face6<Real, D>(a, q, gde1, gde2, ge1, ge2, 1, Fu);  // face between cells 0 and +1
+#pragma unroll
+    for (int c = 0; c < 4; c++) acc[c] += (Fu[c] - Fl[c]) * a.ih[D];
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) visc6_flux_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+                                                         const Real* __restrict__ G, Real* __restrict__ Rv)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.ncell) return;
+    const int i = (int)(t % a.nx);
+    const long long r = t / a.nx;
+    const int j = (int)(r % a.ny), k = (int)(r / a.ny);
+    const int px = a.nx + 6, py = a.ny + 6;
+    const long long tp = ((long long)(k + 3) * py + (j + 3)) * px + (i + 3);
+    Real acc[4] = {0, 0, 0, 0};
+    direction6<Real, 0>(a, Q, G, tp, 1, acc);
+    direction6<Real, 1>(a, Q, G, tp, px, acc);
+    direction6<Real, 2>(a, Q, G, tp, (long long)px * py, acc);
+#pragma unroll
+    for (int c = 0; c < 4; c++) Rv[c * a.ncell + t] = acc[c];
+}
+
+}  // namespace
+
+template <typename Real>
+hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* G, Real* Rv, hipStream_t st)
+{
+    const int nt = 256;
+    const long long bp = (a.npad + nt - 1) / nt, bc = (a.ncell + nt - 1) / nt;
+    hipLaunchKernelGGL(visc6_q_kernel<Real>, dim3((unsigned)bp), dim3(nt), 0, st, a, U, Q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(visc6_grad_kernel<Real>, dim3((unsigned)bp), dim3(nt), 0, st, a, (const Real*)Q, G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(visc6_flux_kernel<Real>, dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
+                       (const Real*)G, Rv);
+    return hipGetLastError();
+}
+
+template hipError_t launch_visc6<double>(const Visc6Args<double>&, const double*, double*, double*, double*,
+                                         hipStream_t);
+template hipError_t launch_visc6<float>(const Visc6Args<float>&, const float*, float*, float*, float*, hipStream_t);
+
+}  // namespace fv

@@ -17,14 +17,14 @@ EULER, NS, DIM = 0, 1, 2
 F64, F32 = 0, 1
 PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
 CASE_UNIFORM, CASE_TGV, CASE_RIEMANN, CASE_SBI = 0, 1, 2, 3
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
-EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rk3_stage",
+EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rhs_ws", "rk3_stage",
             "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "adjoint_workspace_bytes",
             "rk3_step_adjoint", "check_state", "workspace_time",
             "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
@@ -51,8 +51,9 @@ class _Cfg(ctypes.Structure):
         ("eps_rho", ctypes.c_double), ("eps_rhoc2", ctypes.c_double), ("eps_alpha", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
-        ("visc_law", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("visc_law", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("T_ref", ctypes.c_double), ("sutherland", ctypes.c_double), ("gas_R", ctypes.c_double),
+        ("visc_order", ctypes.c_int32), ("thinc", ctypes.c_int32),
     ]
 
 
@@ -86,6 +87,9 @@ class Config:
     weno_eps: float = 0.0
     cfl: float = 0.5
     recon: int = 0          # 0: primitive variables, 1: characteristic variables
+    scheme: int = 0         # 0: WENO5-Z, 1: TENO6-A
+    visc_order: int = 0     # central viscous stencils: 0/4 fused 4th order, 6 sixth order (separate passes)
+    thinc: int = 0          # five-equation model: THINC interface capturing
     visc_law: int = 0       # 0: constant mu, 1: power law, 2: Sutherland (Sec. 2.5)
     T_ref: float = 1.0
     sutherland: float = 0.0
@@ -120,8 +124,9 @@ class Config:
         c.mu, c.prandtl = self.mu, self.prandtl
         c.eps_rho, c.eps_rhoc2, c.eps_alpha = self.eps_rho, self.eps_rhoc2, self.eps_alpha
         c.weno_eps, c.cfl = self.weno_eps, self.cfl
-        c.visc_law, c.reserved = self.visc_law, 0
+        c.visc_law, c.scheme = self.visc_law, self.scheme
         c.T_ref, c.sutherland, c.gas_R = self.T_ref, self.sutherland, self.gas_R
+        c.visc_order, c.thinc = self.visc_order, self.thinc
         return c
 
 
@@ -144,6 +149,7 @@ def lib():
         L.prim_to_cons.argtypes = [cp, vp, vp, vp]
         L.cons_to_prim.argtypes = [cp, vp, vp, vp]
         L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
+        L.rhs_ws.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
         L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
         L.rk3_stage3_cfl.argtypes = [cp, vp, vp, vp, vp, vp, vp, vp]
         L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
@@ -245,11 +251,18 @@ def cons_to_prim(cfg: Config, U: torch.Tensor, W: torch.Tensor, stream=None):
     return W
 
 
-def rhs(cfg: Config, U: torch.Tensor, R: torch.Tensor, dt: float = 0.0, stream=None):
+def rhs(cfg: Config, U: torch.Tensor, R: torch.Tensor, dt: float = 0.0, stream=None, ws=None):
+    """R = R_NSE(U); with a workspace (required for sixth-order viscous fluxes,
+    allocated here if not given) through rhs_ws."""
     _state(cfg, U, "U")
     _state(cfg, R, "R")
     c = cfg.c_struct()
-    _check(lib().rhs(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _stream(stream)))
+    if ws is None and cfg.visc_order == 6:
+        ws = workspace(cfg)
+    if ws is None:
+        _check(lib().rhs(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _stream(stream)))
+    else:
+        _check(lib().rhs_ws(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _ptr(ws), _stream(stream)))
     return R
 
 

@@ -57,6 +57,16 @@ def test_validation_codes():
     assert call_rhs(cfg(), U=256, R=256) == S.EINVAL
     assert call_rhs(cfg(), dt=float("nan")) == S.EINVAL
     assert "dt" in S.last_error()
+    assert call_rhs(cfg(scheme=2)) == S.EINVAL
+    assert "scheme" in S.last_error()
+    assert call_rhs(cfg(recon=2)) == S.EINVAL
+    assert call_rhs(cfg(visc_order=5)) == S.EINVAL
+    assert call_rhs(cfg(visc_order=6)) == S.EINVAL            # sixth order is for the viscous model
+    assert call_rhs(cfg(model=S.NS, mu=0.01, visc_order=6)) == S.EUNSUPPORTED   # needs rhs_ws
+    assert "rhs_ws" in S.last_error()
+    c6 = cfg(model=S.NS, mu=0.01, visc_order=6).c_struct()
+    assert S.lib().rk3_stage(ctypes.byref(c6), 1, 256, 256, 512, 1e-3, None, None) == S.EUNSUPPORTED
+    assert S.lib().rhs_ws(ctypes.byref(c6), 256, 512, 0.0, None, None) == S.ENULL
     c = cfg().c_struct()
     c.abi_version = 99
     assert S.lib().rhs(ctypes.byref(c), 256, 512, 0.0, None) == S.EINVAL
@@ -76,7 +86,8 @@ def test_stage_and_step_validation():
     c2 = cfg(cfl=0.0).c_struct()
     assert L.advance(ctypes.byref(c2), 256, 3, 0.0, None, 512, None) == S.EINVAL
     # the adjoint covers single-phase Euler, FP64, limiters off
-    for bad in (cfg(model=S.NS, mu=0.01), cfg(model=S.DIM), cfg(dtype=S.F32), cfg(positivity=1)):
+    for bad in (cfg(model=S.NS, mu=0.01), cfg(model=S.DIM), cfg(dtype=S.F32), cfg(positivity=1), cfg(recon=1),
+                cfg(scheme=1)):
         cb = bad.c_struct()
         assert L.rhs_adjoint(ctypes.byref(cb), 256, 512, 768, None, None) == S.EUNSUPPORTED
         assert L.rk3_step_adjoint(ctypes.byref(cb), 256, 512, 1e-3, 768, None) == S.EUNSUPPORTED
@@ -90,6 +101,11 @@ def test_stage_and_step_validation():
 
 
 def test_workspace_and_ncomp():
+    c6 = cfg(nx=10, ny=3, nz=2, model=S.NS, mu=0.01, visc_order=6)
+    a256 = lambda b: (b + 255) // 256 * 256
+    npad, n = 16 * 9 * 8, 60
+    assert S.workspace_bytes(c6) == 2 * a256(8 * 5 * n) + 256 + a256(4 * npad * 8) + a256(9 * npad * 8) + \
+        a256(4 * n * 8)
     c = cfg(nx=10, ny=3, nz=2)
     state = 8 * 5 * 60
     pad = (state + 255) // 256 * 256
