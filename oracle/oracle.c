@@ -17,7 +17,7 @@
  * divergence of Eq. (FVD) plus the volume-fraction source of Sec. 3.6, and
  * the TVD-RK3 scheme of Sec. 3.4.
  *
- * Readings where the paper is silent or garbled (each listed in the design doc):
+ * Readings where the paper is silent or garbled:
  *  - reconstruction acts on primitive variables component by component;
  *  - WENO-Z uses q = 1 and a configurable epsilon;
  *  - the p_k stencils follow the figure of the reconstruction schematic
