@@ -304,6 +304,31 @@ def sod_tube(n: int = 200) -> Case:
 # --------------------------------------------------------------------------
 # Shock-bubble interaction
 # --------------------------------------------------------------------------
+def interface_advection(n: int = 48, axis: int = 0, flip: bool = False, u: float = 0.5) -> Case:
+    """Two smeared helium/air interfaces (tanh profiles a few cells wide) in a
+    periodic line along `axis`, advected at uniform velocity and pressure: the
+    five-equation model with an interface band of about eight cells
+    (volume fraction between 1e-6 and 1 - 1e-6).  `flip` mirrors the field and
+    the velocity."""
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    x = (np.arange(n) + 0.5) / n
+    a = 0.5 * (1 + np.tanh((x - 0.3) * n / 2.0)) * 0.5 * (1 - np.tanh((x - 0.7) * n / 2.0))
+    a = 1e-6 + (1 - 2e-6) * a
+    if flip:
+        a = a[::-1].copy()
+    W = np.zeros((7, *shape))
+    r1, r2 = 0.166, 1.2
+    W[0] = (a * r1).reshape(shape)
+    W[1] = ((1 - a) * r2).reshape(shape)
+    W[2 + axis] = -u if flip else u
+    W[5] = 1.0
+    W[6] = a.reshape(shape)
+    h = 1.0 / n
+    return Case(name=f"interface_{'xyz'[axis]}_{n}", nx=shape[2], ny=shape[1], nz=shape[0], dx=h, dy=h, dz=h,
+                model=DIM, bc=(PERIODIC,) * 6, W=W, gamma1=1.66, gamma2=1.4, positivity=1)
+
+
 def rankine_hugoniot(ma: float, gamma: float, rho1: float, p1: float, pinf: float = 0.0):
     """Post-shock (rho2, u2, p2) behind a shock of Mach number ma moving into
     fluid at rest (rho1, p1), stiffened gas; returns (rho2, u2, p2, shock_speed)."""

@@ -13,22 +13,10 @@ import oracle as O
 from paper_2402_05193_amd import solver as S
 from paper_2402_05193_amd import workloads as WL
 from test_gpu_parity import RHS_TOL, comp_rel, dev, host, oracle_cfg, roundoff_floor, solver_cfg
-from test_oracle_thinc import interface_case
 
 pytestmark = pytest.mark.gpu
 
 MIXED_BC = (WL.PERIODIC, WL.PERIODIC, WL.ZERO_GRADIENT, WL.ZERO_GRADIENT, WL.SYMMETRY, WL.SYMMETRY)
-
-
-class _Case:
-    """A case from primitive fields and oracle keyword arguments."""
-
-    def __init__(self, W, kw):
-        self.W = W
-        self._kw = kw
-
-    def cfg_kwargs(self):
-        return dict(self._kw)
 
 
 def cases():
@@ -39,8 +27,7 @@ def cases():
         "dim_sbi": WL.shock_bubble(48, 24, 24),
     }
     for axis in (0, 1, 2):
-        W, kw = interface_case(40, axis=axis)
-        c[f"interface_{'xyz'[axis]}"] = _Case(W, kw)
+        c[f"interface_{'xyz'[axis]}"] = WL.interface_advection(40, axis=axis)
     return c
 
 

@@ -35,25 +35,9 @@ def test_profile_average_and_face_values(abar, theta, beta):
 
 
 def interface_case(n=48, axis=0, flip=False, u=0.5):
-    """A smeared air/helium interface (tanh over a few cells) advected at uniform
-    velocity and pressure, periodic: two interfaces."""
-    shape = [1, 1, 1]
-    shape[2 - axis] = n
-    x = (np.arange(n) + 0.5) / n
-    a = 0.5 * (1 + np.tanh((x - 0.3) * n / 2.0)) * 0.5 * (1 - np.tanh((x - 0.7) * n / 2.0))
-    a = 1e-6 + (1 - 2e-6) * a
-    if flip:
-        a = a[::-1].copy()
-    W = np.zeros((7, *shape))
-    r1, r2 = 0.166, 1.2
-    W[0] = (a * r1).reshape(shape)
-    W[1] = ((1 - a) * r2).reshape(shape)
-    W[2 + axis] = -u if flip else u
-    W[5] = 1.0
-    W[6] = a.reshape(shape)
-    kw = dict(nx=shape[2], ny=shape[1], nz=shape[0], dx=1.0 / n, dy=1.0 / n, dz=1.0 / n, model=O.DIM,
-              gamma1=1.66, gamma2=1.4, positivity=1)
-    return W, kw
+    """(W, oracle Config keyword arguments) of the interface advection workload."""
+    case = WL.interface_advection(n, axis=axis, flip=flip, u=u)
+    return case.W, case.cfg_kwargs()
 
 
 def test_only_interface_faces_change():
