@@ -162,9 +162,30 @@ def run_oracle_baseline(n: int, model: int) -> dict:
     O.rk3_step(cfg, U, dt)
     el = time.perf_counter() - t0
     cells = cfg.nx * cfg.ny * cfg.nz
+    # the same on one thread, on a 64^3 block of the workload's kind (a few seconds)
+    small = WL.taylor_green(64, viscous=(model == 1)) if model != 2 else WL.shock_bubble(64, 32, 32)
+    cs = O.Config(**small.cfg_kwargs())
+    Us = O.prim_to_cons(cs, small.W)
+    O.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        O.rk3_step(cs, Us, O.compute_dt(cs, Us, 0.5))
+        el1 = time.perf_counter() - t1
+    finally:
+        O.set_threads(threads)
+    cells1 = cs.nx * cs.ny * cs.nz
+    model_name = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model_name = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": cells * 3 / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one TVD-RK3 step (3 stages) of the same workload, {cfg.nx}x{cfg.ny}x{cfg.nz} FP64, "
-                      f"{el:.1f} s on {threads} threads"}
+                      f"{el:.1f} s on {threads} threads",
+            "single_thread": {"value": cells1 * 3 / el1, "sample": f"one TVD-RK3 step at {cs.nx}x{cs.ny}x{cs.nz}, "
+                                                                  f"{el1:.1f} s on 1 thread"},
+            "cpu_model": model_name}
 
 
 def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: int = 2402,
@@ -412,6 +433,18 @@ def main():
     hbm_gbs = alg_bytes / (mean_stage_ms * 1e-3) / 1e9
 
     finite = bool(torch.isfinite(U).all().item())
+    # a device copy of 1 GiB timed like the stages: the HBM rate a streaming kernel attains here
+    cbuf = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        cdst.copy_(cbuf)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * cbuf.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del cbuf, cdst
     default_kernel = (model == S.NS and dtype == S.F64 and args.recon == 0 and args.scheme == 0
                       and cfg.visc_order != 6)
     workload_key = (f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
@@ -440,7 +473,9 @@ def main():
                      "frac": achieved_tflops / peak, "traffic": traffic,
                      "kernel": "stage_kernel", "flops_per_cell": fpc, "kernel_fingerprint": stage_kernel_hash() if default_kernel else None},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell},
+                         "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell,
+                         "measured_copy_gbs": copy_gbs, "frac_of_copy": hbm_gbs / copy_gbs,
+                         "traffic_gbs": (traffic / (mean_stage_ms * 1e-3) / 1e9) if traffic else None},
         "wall_s": wall,
         "state_finite": finite,
     }
