@@ -38,6 +38,14 @@ size_t state_bytes(const fv_config* c)
     return es * (size_t)ncomp_of(c->model) * (size_t)c->nx * (size_t)c->ny * (size_t)c->nz;
 }
 
+// workgroups a stage launch aims at (tile columns x z chunks), FP64; FP32 twice
+// as many (its kernels hold fewer registers, more workgroups fit a CU).
+// Measured at 256^3 (NS, stage ms): FP64 512 / 1024 / 2048 / 4096 workgroups
+// 2.58 / 2.54 / 2.51 / 2.53; FP32 1.85 / 1.68 / 1.39 / 1.36.
+#ifndef FV_TARGET_WORKGROUPS
+#define FV_TARGET_WORKGROUPS 2048
+#endif
+
 constexpr size_t SCALAR_BYTES = 256;  // dt, inverse-dt max, time accumulator, check words
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -173,7 +181,7 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.tiles_y = (c->ny + TILE_BY - 1) / TILE_BY;
     // z chunks: enough workgroups to fill 256 CUs several times over
     const long long tiles = (long long)a.tiles_x * a.tiles_y;
-    const long long target = 2048;
+    const long long target = f64 ? FV_TARGET_WORKGROUPS : 2 * FV_TARGET_WORKGROUPS;
     int nch = (int)((target + tiles - 1) / tiles);
     if (nch < 1) nch = 1;
     int zc = (c->nz + nch - 1) / nch;
