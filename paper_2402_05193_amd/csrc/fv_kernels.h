@@ -53,8 +53,9 @@ namespace fv {
 enum { REC_WENO_PRIM = 0, REC_WENO_CHAR = 1, REC_TENO_PRIM = 2, REC_TENO_CHAR = 3 };
 // Viscous variants of the viscous model: constant viscosity, a viscosity law
 // (both 4th-order fluxes inside the stage), or sixth-order fluxes from the
-// separate passes of fv_visc6.hip (any law)
-enum { VM_CONST = 0, VM_LAW = 1, VM_EXT = 2 };
+// separate passes of fv_visc6.hip (constant viscosity / a law: the law only
+// enters the stage's CFL reduction)
+enum { VM_CONST = 0, VM_LAW = 1, VM_EXT = 2, VM_EXT_LAW = 3 };
 // and of the five-equation model: THINC interface capturing off / on
 enum { XM_PLAIN = 0, XM_THINC = 1 };
 

@@ -134,7 +134,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
 {
     using L = Layout<MODEL>;
     constexpr bool THINC = MODEL == DIM && VMODE == XM_THINC;
-    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT, THINC>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT && VMODE != VM_EXT_LAW, THINC>;
     constexpr bool VLAW = MODEL == NS && VMODE == VM_LAW;
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
@@ -512,7 +512,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
                     }
                     if constexpr (MODEL == DIM) r[6] += win[1 + WO][6] * (srcA + (uh - uhzl) * idz);
-                    if constexpr (MODEL == NS && VMODE == VM_EXT) {
+                    if constexpr (MODEL == NS && (VMODE == VM_EXT || VMODE == VM_EXT_LAW)) {
                         // divergence of the sixth-order viscous fluxes (separate passes)
 #pragma unroll
                         for (int c = 0; c < 3; c++) r[V + c] += a.rvisc[c * a.ncell + q];
@@ -527,7 +527,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         }
                     }
                     store_cell_impl<Real, NC>(a, q, r, dt, pre_k, pre_n, unew);
-                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, VMODE != VM_CONST>(a, unew));
+                    if (a.inv_max) tmax = fmax(tmax, inverse_dt<Real, MODEL, MODEL == NS && (VMODE == VM_LAW || VMODE == VM_EXT_LAW)>(a, unew));
                 }
 #pragma unroll
                 for (int m = 0; m < NC; m++) Fzl[m] = F[m];
@@ -894,7 +894,8 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU)
 template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT, MODEL == DIM && VMODE == XM_THINC>;
+    using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT && VMODE != VM_EXT_LAW,
+                    MODEL == DIM && VMODE == XM_THINC>;
     const size_t lds = TL::bytes();
     static bool attr_set = false;
     if (!attr_set) {
@@ -940,7 +941,9 @@ hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStr
     // pow() must not weigh on the constant-viscosity kernel; sixth-order viscous
     // fluxes come from separate passes (the stage adds them)
     if constexpr (MODEL == NS) {
-        if (args.rvisc) return launch_variant<Real, MODEL, VM_EXT>(args, g, st);
+        if (args.rvisc)
+            return args.vl.law != 0 ? launch_variant<Real, MODEL, VM_EXT_LAW>(args, g, st)
+                                    : launch_variant<Real, MODEL, VM_EXT>(args, g, st);
         if (args.vl.law != 0) return launch_variant<Real, MODEL, VM_LAW>(args, g, st);
     }
     if constexpr (MODEL == DIM) {

@@ -96,22 +96,20 @@ __global__ void __launch_bounds__(256) visc6_grad_kernel(const Visc6Args<Real> a
     }
 }
 
-// viscous flux (tau_x, tau_y, tau_z, u . tau + kappa dtheta/dn) of the d-face whose
-// six cells across are q[*][b .. b+5] and g*[b .. b+5]
-template <typename Real, int D>
-__device__ __forceinline__ void face6(const Visc6Args<Real>& a, const Real (*q)[7], const Real* gde1, const Real* gde2,
-                                      const Real* ge1, const Real* ge2, int b, Real* F)
+// viscous flux (tau_x, tau_y, tau_z, u . tau + kappa dtheta/dn) of a d-face from its
+// face values vf, normal derivatives dn (u, v, w, theta), face temperature thf and the
+// interpolated tangential derivatives t_de1, t_de2 (d u_D / d x_E), t_e1, t_e2 (d u_E / d x_E)
+template <typename Real, int D, int LAW>
+__device__ __forceinline__ void face6(const Visc6Args<Real>& a, const Real* vf, const Real* dn, Real thf,
+                                      Real t_de1, Real t_de2, Real t_e1, Real t_e2, Real* F)
 {
     constexpr int E1 = (D + 1) % 3, E2 = (D + 2) % 3;
-    Real vf[3], dn[4];
-#pragma unroll
-    for (int c = 0; c < 3; c++) vf[c] = ifc6(q[c] + b);
-#pragma unroll
-    for (int c = 0; c < 4; c++) dn[c] = dface6(q[c] + b, a.ih[D]);
-    const Real thf = ifc6(q[3] + b);
-    const Real t_de1 = ifc6(gde1 + b), t_de2 = ifc6(gde2 + b);
-    const Real div = dn[D] + ifc6(ge1 + b) + ifc6(ge2 + b);
-    const Real mu = visc_mu(a.vl, thf);
+    const Real div = dn[D] + t_e1 + t_e2;
+    // constant viscosity without the law's code (the power law's pow, inlined at six
+    // faces, would take the registers of the whole kernel)
+    Real mu;
+    if constexpr (LAW == 0) mu = a.vl.mu;
+    else mu = visc_mu(a.vl, thf);
     const Real kap = mu * a.vl.kfac;
     Real tau[3];
     tau[D] = mu * (Real(2) * dn[D] - Real(2.0 / 3.0) * div);
@@ -123,30 +121,48 @@ __device__ __forceinline__ void face6(const Visc6Args<Real>& a, const Real (*q)[
     F[3] = vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2] + kap * dn[3];
 }
 
-template <typename Real, int D>
+// both d-faces of the cell at padded index tp (axis stride s): the seven cells along
+// the axis are read one field at a time and reduced to the two faces' values at once,
+// so that only one field's stencil is live
+template <typename Real, int D, int LAW>
 __device__ __forceinline__ void direction6(const Visc6Args<Real>& a, const Real* __restrict__ Q,
                                            const Real* __restrict__ G, long long tp, long long s, Real* acc)
 {
     constexpr int E1 = (D + 1) % 3, E2 = (D + 2) % 3;
-    Real q[4][7], gde1[7], gde2[7], ge1[7], ge2[7];
+    Real vf[2][3], dn[2][4], th[2], t[4][2];
+    auto load7 = [&](const Real* base, Real* v) {
 #pragma unroll
-    for (int o = 0; o < 7; o++) {
-        const long long x = tp + (o - 3) * s;
+        for (int o = 0; o < 7; o++) v[o] = base[tp + (o - 3) * s];
+    };
 #pragma unroll
-        for (int c = 0; c < 4; c++) q[c][o] = Q[c * a.npad + x];
-        gde1[o] = G[(3 * D + E1) * a.npad + x];
-        gde2[o] = G[(3 * D + E2) * a.npad + x];
-        ge1[o] = G[(3 * E1 + E1) * a.npad + x];
-        ge2[o] = G[(3 * E2 + E2) * a.npad + x];
+    for (int c = 0; c < 4; c++) {
+        Real v[7];
+        load7(Q + c * a.npad, v);
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            dn[b][c] = dface6(v + b, a.ih[D]);
+            if (c < 3) vf[b][c] = ifc6(v + b);
+            else th[b] = ifc6(v + b);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one field's stencil live at a time
+    }
+    const int gi[4] = {3 * D + E1, 3 * D + E2, 3 * E1 + E1, 3 * E2 + E2};
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        Real v[7];
+        load7(G + gi[g] * a.npad, v);
+#pragma unroll
+        for (int b = 0; b < 2; b++) t[g][b] = ifc6(v + b);
+        __builtin_amdgcn_sched_barrier(0);
     }
     Real Fl[4], Fu[4];
-    face6<Real, D>(a, q, gde1, gde2, ge1, ge2, 0, Fl);  // face between cells -1 and 0
-    face6<Real, D>(a, q, gde1, gde2, ge1, ge2, 1, Fu);  // face between cells 0 and +1
+    face6<Real, D, LAW>(a, vf[0], dn[0], th[0], t[0][0], t[1][0], t[2][0], t[3][0], Fl);  // face between cells -1, 0
+    face6<Real, D, LAW>(a, vf[1], dn[1], th[1], t[0][1], t[1][1], t[2][1], t[3][1], Fu);  // face between cells 0, +1
 #pragma unroll
     for (int c = 0; c < 4; c++) acc[c] += (Fu[c] - Fl[c]) * a.ih[D];
 }
 
-template <typename Real>
+template <typename Real, int LAW>
 __global__ void __launch_bounds__(256) visc6_flux_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
                                                          const Real* __restrict__ G, Real* __restrict__ Rv)
 {
@@ -158,9 +174,9 @@ __global__ void __launch_bounds__(256) visc6_flux_kernel(const Visc6Args<Real> a
     const int px = a.nx + 6, py = a.ny + 6;
     const long long tp = ((long long)(k + 3) * py + (j + 3)) * px + (i + 3);
     Real acc[4] = {0, 0, 0, 0};
-    direction6<Real, 0>(a, Q, G, tp, 1, acc);
-    direction6<Real, 1>(a, Q, G, tp, px, acc);
-    direction6<Real, 2>(a, Q, G, tp, (long long)px * py, acc);
+    direction6<Real, 0, LAW>(a, Q, G, tp, 1, acc);
+    direction6<Real, 1, LAW>(a, Q, G, tp, px, acc);
+    direction6<Real, 2, LAW>(a, Q, G, tp, (long long)px * py, acc);
 #pragma unroll
     for (int c = 0; c < 4; c++) Rv[c * a.ncell + t] = acc[c];
 }
@@ -177,8 +193,12 @@ hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(visc6_grad_kernel<Real>, dim3((unsigned)bp), dim3(nt), 0, st, a, (const Real*)Q, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(visc6_flux_kernel<Real>, dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
-                       (const Real*)G, Rv);
+    if (a.vl.law == 0)
+        hipLaunchKernelGGL((visc6_flux_kernel<Real, 0>), dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
+    else
+        hipLaunchKernelGGL((visc6_flux_kernel<Real, 1>), dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
     return hipGetLastError();
 }
 
