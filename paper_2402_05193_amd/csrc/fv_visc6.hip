@@ -19,8 +19,10 @@
 //      tangential derivatives interpolated from the gradients of pass 2; the
 //      stress tensor with the viscosity of the face temperature, the heat flux
 //      with the constant-Prandtl conductivity; then their divergence.
-// Passes 2 and 3 read neighbours along one axis at a time from contiguous
-// arrays (x fastest); the L1/L2 caches serve the reuse.
+// Pass 2 runs once per axis on line tiles staged in LDS (16 lines of 32 cells
+// plus the 3-cell halo), so that each value is read from memory about once per
+// axis; pass 3 reads its stencils directly (x fastest), the caches serving the
+// reuse (staging its eight fields per axis cost more DRAM traffic than it saved).
 #include <hip/hip_runtime.h>
 
 #include "fv_kernels.h"
@@ -70,28 +72,69 @@ __global__ void __launch_bounds__(256) visc6_q_kernel(const Visc6Args<Real> a, c
     Q[3 * a.npad + t] = w[4] * rcp(w[0]);
 }
 
+// ---- line tiles: a workgroup stages LNS lines of SPAN cells along one axis in LDS
+// (the LEN cells it works on and 3 on either side) and reads every stencil there.
+// Lines run along AX; the line coordinate is y for AX = 0 and x otherwise, the
+// third coordinate z for AX = 0, 1 and y for AX = 2.  Consecutive lanes take
+// consecutive x: along the line for AX = 0, across the lines otherwise.
+constexpr int LNS = 16, LEN = 32, SPAN = LEN + 6, NTT = 256;
+
+template <int AX>
+__device__ __forceinline__ void tile_cell(int ax, int line, int third, int& x, int& y, int& z)
+{
+    if constexpr (AX == 0) { x = ax; y = line; z = third; }
+    else if constexpr (AX == 1) { x = line; y = ax; z = third; }
+    else { x = line; y = third; z = ax; }
+}
+
 template <typename Real>
-__global__ void __launch_bounds__(256) visc6_grad_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+__device__ __forceinline__ long long padded_index(const Visc6Args<Real>& a, int x, int y, int z)
+{
+    return ((long long)(z + 3) * (a.ny + 6) + (y + 3)) * (a.nx + 6) + (x + 3);
+}
+
+// (line slot, position) of item `it` of a tile: x fastest across the lanes
+template <int AX, int NP>
+__device__ __forceinline__ void tile_item(int it, int& l, int& p)
+{
+    if constexpr (AX == 0) { p = it % NP; l = it / NP; }
+    else { l = it % LNS; p = it / LNS; }
+}
+
+// du_c/dx_E (c = 0, 1, 2) at the padded cells whose E-coordinate is interior, over the
+// whole padded range of the other two coordinates
+template <typename Real, int E>
+__global__ void __launch_bounds__(NTT) visc6_grad_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
                                                          Real* __restrict__ G)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.npad) return;
-    const int px = a.nx + 6, py = a.ny + 6;
-    const int i = (int)(t % px) - 3;
-    const long long r = t / px;
-    const int j = (int)(r % py) - 3, k = (int)(r / py) - 3;
-    const int c3[3] = {i, j, k}, n3[3] = {a.nx, a.ny, a.nz};
-    const long long s3[3] = {1, px, (long long)px * py};
-#pragma unroll
-    for (int e = 0; e < 3; e++) {
-        if (c3[e] < 0 || c3[e] >= n3[e]) continue;
-        const long long s = s3[e];
-        const Real f = a.ih[e] * Real(1.0 / 60.0);
+    __shared__ Real S[3][LNS][SPAN];
+    const int n3[3] = {a.nx, a.ny, a.nz};
+    const int nax = n3[E], nline = E == 0 ? a.ny : a.nx;  // lines over the padded range [-3, nline + 3)
+    const int a0 = blockIdx.x * LEN, l0 = (int)blockIdx.y * LNS - 3, third = (int)blockIdx.z - 3;
+    for (int it = threadIdx.x; it < 3 * LNS * SPAN; it += NTT) {
+        const int c = it / (LNS * SPAN);
+        int l, p;
+        tile_item<E, SPAN>(it - c * LNS * SPAN, l, p);
+        const int ax = a0 + p - 3, line = l0 + l;
+        if (ax > nax + 2 || line >= nline + 3) continue;  // beyond the padded box
+        int x, y, z;
+        tile_cell<E>(ax, line, third, x, y, z);
+        S[c][l][p] = Q[c * a.npad + padded_index(a, x, y, z)];
+    }
+    __syncthreads();
+    const Real f = a.ih[E] * Real(1.0 / 60.0);
+    for (int it = threadIdx.x; it < LNS * LEN; it += NTT) {
+        int l, p;
+        tile_item<E, LEN>(it, l, p);
+        const int ax = a0 + p, line = l0 + l;
+        if (ax >= nax || line >= nline + 3) continue;
+        int x, y, z;
+        tile_cell<E>(ax, line, third, x, y, z);
+        const long long q = padded_index(a, x, y, z);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            const Real* q = Q + c * a.npad + t;
-            G[(3 * c + e) * a.npad + t] =
-                (Real(45) * (q[s] - q[-s]) - Real(9) * (q[2 * s] - q[-2 * s]) + (q[3 * s] - q[-3 * s])) * f;
+            const Real* v = &S[c][l][p + 3];
+            G[(3 * c + E) * a.npad + q] = (Real(45) * (v[1] - v[-1]) - Real(9) * (v[2] - v[-2]) + (v[3] - v[-3])) * f;
         }
     }
 }
@@ -186,18 +229,27 @@ __global__ void __launch_bounds__(256) visc6_flux_kernel(const Visc6Args<Real> a
 template <typename Real>
 hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* G, Real* Rv, hipStream_t st)
 {
-    const int nt = 256;
-    const long long bp = (a.npad + nt - 1) / nt, bc = (a.ncell + nt - 1) / nt;
-    hipLaunchKernelGGL(visc6_q_kernel<Real>, dim3((unsigned)bp), dim3(nt), 0, st, a, U, Q);
+    const long long bp = (a.npad + NTT - 1) / NTT;
+    hipLaunchKernelGGL(visc6_q_kernel<Real>, dim3((unsigned)bp), dim3(NTT), 0, st, a, U, Q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(visc6_grad_kernel<Real>, dim3((unsigned)bp), dim3(nt), 0, st, a, (const Real*)Q, G);
+    // gradients along x (lines along x over the padded y, z range), along y and z (lines
+    // along those axes, across the padded x range)
+    hipLaunchKernelGGL((visc6_grad_kernel<Real, 0>), dim3((a.nx + LEN - 1) / LEN, (a.ny + 6 + LNS - 1) / LNS, a.nz + 6),
+                       dim3(NTT), 0, st, a, (const Real*)Q, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((visc6_grad_kernel<Real, 1>), dim3((a.ny + LEN - 1) / LEN, (a.nx + 6 + LNS - 1) / LNS, a.nz + 6),
+                       dim3(NTT), 0, st, a, (const Real*)Q, G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((visc6_grad_kernel<Real, 2>), dim3((a.nz + LEN - 1) / LEN, (a.nx + 6 + LNS - 1) / LNS, a.ny + 6),
+                       dim3(NTT), 0, st, a, (const Real*)Q, G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned bc = (unsigned)((a.ncell + NTT - 1) / NTT);
     if (a.vl.law == 0)
-        hipLaunchKernelGGL((visc6_flux_kernel<Real, 0>), dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
+        hipLaunchKernelGGL((visc6_flux_kernel<Real, 0>), dim3(bc), dim3(NTT), 0, st, a, (const Real*)Q,
                            (const Real*)G, Rv);
     else
-        hipLaunchKernelGGL((visc6_flux_kernel<Real, 1>), dim3((unsigned)bc), dim3(nt), 0, st, a, (const Real*)Q,
+        hipLaunchKernelGGL((visc6_flux_kernel<Real, 1>), dim3(bc), dim3(NTT), 0, st, a, (const Real*)Q,
                            (const Real*)G, Rv);
     return hipGetLastError();
 }
