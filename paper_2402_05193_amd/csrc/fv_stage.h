@@ -271,6 +271,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         if (need_plane) {
             // halo cell of this thread (at most one: NHALO <= NT), loaded before the barrier
             static_assert(TL::NHALO <= NT, "one halo cell per thread");
+            Real vz[2][3];           // viscous halo column: (rho, rho u_a, rho w) at two planes
+            int vc_i = 0, vc_j = 0;  // its tile coordinates
             int hi = 0, hj = 0;
             Real hu[NC];
             const bool has_halo = tid < TL::NHALO;
@@ -296,6 +298,48 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     hj = (hh & 2) ? BY : -1;
                 }
                 if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+            }
+            // viscous: the halo columns of the viscous regions need d/dz of two velocity
+            // components at plane s; a pair of threads shares a column, the even one
+            // loading planes s-2, s-1 and the odd one s+1, s+2 (issued here, reduced
+            // after the halo ring is staged)
+            if constexpr (VISC) {
+                static_assert(2 * (4 * BY + 4 * BX) <= NT, "two threads per viscous halo column");
+                if (xy && tid < 2 * (4 * BY + 4 * BX)) {
+                    const int h = tid >> 1, odd = tid & 1;
+                    int i, j;
+                    if (h < 4 * BY) {
+                        j = h / 4;
+                        const int k = h % 4;
+                        i = k < 2 ? k - 2 : BX + k - 2;
+                    } else {
+                        const int hh = h - 4 * BY;
+                        i = hh % BX;
+                        const int k = hh / BX;
+                        j = k < 2 ? k - 2 : BY + k - 2;
+                    }
+                    vc_i = i;
+                    vc_j = j;
+                    const int ca = h < 4 * BY ? V : V + 1;  // u on the x region, v on the y region; then w
+                    bool fx = false, fy = false;
+                    const int ii = interior_xy ? x0 + i : map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
+                    const int jj = interior_xy ? y0 + j : map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
+                    const bool fa = h < 4 * BY ? fx : fy;
+#pragma unroll
+                    for (int p = 0; p < 2; p++) {
+                        bool fz = false;
+                        const int kk = map_index(s + (odd ? p + 1 : p - 2), a.nz, a.bc[4], a.bc[5], fz);
+                        const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
+                        vz[p][0] = a.Uk[qq];
+                        vz[p][1] = fa ? -a.Uk[ca * a.ncell + qq] : a.Uk[ca * a.ncell + qq];
+                        vz[p][2] = fz ? -a.Uk[(V + 2) * a.ncell + qq] : a.Uk[(V + 2) * a.ncell + qq];
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < 2; p++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) vz[p][c] = Real(1);
+                }
             }
             // the plane buffer is overwritten below: after a step with x/y phases their
             // barriers already ordered every read of it; after a warm-up step (only the
@@ -356,45 +400,24 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         DZY[0 * TL::RY + (ty + 2) * BX + tx] = dz[1];
                         DZY[1 * TL::RY + (ty + 2) * BX + tx] = dz[2];
                     }
-                    // halo columns of the viscous regions: from memory, taken by the
-                    // highest-numbered threads (the regular halo ring uses the lowest)
-                    for (int h = NT - 1 - tid; h < 4 * BY + 4 * BX && h >= 0; h += NT) {
-                        int i, j;
-                        if (h < 4 * BY) {
-                            j = h / 4;
-                            const int k = h % 4;
-                            i = k < 2 ? k - 2 : BX + k - 2;
-                        } else {
-                            const int hh = h - 4 * BY;
-                            i = hh % BX;
-                            const int k = hh / BX;
-                            j = k < 2 ? k - 2 : BY + k - 2;
-                        }
-                        // velocities of planes s-2, s-1, s+1, s+2 (density and momenta only)
-                        Real vel[4][3];
+                    // halo columns of the viscous regions (loads issued at the start of the
+                    // step): velocities at the thread's two planes, then the pair swaps half
+                    // of them so that the even thread differentiates the first component
+                    // (u or v) and the odd one w, each from all four planes
+                    const int odd = tid & 1;
+                    Real va[2], vb[2];
 #pragma unroll
-                        for (int k = 0; k < 4; k++) {
-                            const int dk = k < 2 ? k - 2 : k - 1;
-                            bool fx = false, fy = false, fz = false;
-                            const int ii = interior_xy ? x0 + i : map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
-                            const int jj = interior_xy ? y0 + j : map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
-                            const int kk = map_index(s + dk, a.nz, a.bc[4], a.bc[5], fz);
-                            const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
-                            const Real ir = rcp(a.Uk[qq]);
-                            vel[k][0] = (fx ? -a.Uk[V * a.ncell + qq] : a.Uk[V * a.ncell + qq]) * ir;
-                            vel[k][1] = (fy ? -a.Uk[(V + 1) * a.ncell + qq] : a.Uk[(V + 1) * a.ncell + qq]) * ir;
-                            vel[k][2] = (fz ? -a.Uk[(V + 2) * a.ncell + qq] : a.Uk[(V + 2) * a.ncell + qq]) * ir;
-                        }
-                        Real d[3];
-#pragma unroll
-                        for (int c = 0; c < 3; c++) d[c] = dcell(vel[0][c], vel[1][c], vel[2][c], vel[3][c], i12);
-                        if (h < 4 * BY) {
-                            DZX[0 * TL::RX + j * (BX + 4) + i + 2] = d[0];
-                            DZX[1 * TL::RX + j * (BX + 4) + i + 2] = d[2];
-                        } else {
-                            DZY[0 * TL::RY + (j + 2) * BX + i] = d[1];
-                            DZY[1 * TL::RY + (j + 2) * BX + i] = d[2];
-                        }
+                    for (int p = 0; p < 2; p++) {
+                        const Real ir = rcp(vz[p][0]);
+                        va[p] = vz[p][1] * ir;
+                        vb[p] = vz[p][2] * ir;
+                    }
+                    const Real y0 = __shfl_xor(odd ? va[0] : vb[0], 1, 64);
+                    const Real y1 = __shfl_xor(odd ? va[1] : vb[1], 1, 64);
+                    if (tid < 2 * (4 * BY + 4 * BX)) {
+                        const Real d = odd ? dcell(y0, y1, vb[0], vb[1], i12) : dcell(va[0], va[1], y0, y1, i12);
+                        if ((tid >> 1) < 4 * BY) DZX[odd * TL::RX + vc_j * (BX + 4) + vc_i + 2] = d;
+                        else DZY[odd * TL::RY + (vc_j + 2) * BX + vc_i] = d;
                     }
                 }
             }
