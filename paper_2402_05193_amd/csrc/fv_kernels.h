@@ -20,6 +20,9 @@
 #ifndef WAVES_PER_EU
 #define WAVES_PER_EU 2
 #endif
+#ifndef WAVES_PER_EU_F32
+#define WAVES_PER_EU_F32 3
+#endif
 #ifndef FV_PREFETCH_RK
 #define FV_PREFETCH_RK 0
 #endif

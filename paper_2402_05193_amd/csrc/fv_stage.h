@@ -881,8 +881,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 }
 
+// Waves per SIMD the stage kernels are compiled for: two in FP64 (256 registers per
+// lane), three in FP32 (168), where the narrower state leaves room for a third
+template <typename Real>
+constexpr int stage_waves()
+{
+    return sizeof(Real) == 4 ? WAVES_PER_EU_F32 : WAVES_PER_EU;
+}
+
 template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
-__global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArgs<Real> a)
+__global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 #if FV_KERNARG_INPLACE
@@ -898,7 +906,7 @@ __global__ void __launch_bounds__(NTH, WAVES_PER_EU) stage_kernel(const StageArg
 // first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
 // and limiter setting for every problem of the launch).
 template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
-__global__ void __launch_bounds__(NTH, WAVES_PER_EU)
+__global__ void __launch_bounds__(NTH, stage_waves<Real>())
     batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first, const int n)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
