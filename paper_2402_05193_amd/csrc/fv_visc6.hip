@@ -21,9 +21,12 @@
 //      with the constant-Prandtl conductivity; then their divergence.
 // Pass 2 runs once per axis on line tiles staged in LDS (16 lines of 32 cells
 // plus the 3-cell halo), so that each value is read from memory about once per
-// axis; pass 3 reads its stencils directly (x fastest), the caches serving the
-// reuse (staging its eight fields per axis cost more DRAM traffic than it saved).
+// axis.  Pass 3 is two kernels: the x and y faces of 16 x 16 column tiles read
+// their stencils directly (the caches serving the reuse), and the z faces march
+// through the columns with their stencils in registers.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "fv_kernels.h"
 #include "fv_physics.h"
@@ -205,23 +208,103 @@ __device__ __forceinline__ void direction6(const Visc6Args<Real>& a, const Real*
     for (int c = 0; c < 4; c++) acc[c] += (Fu[c] - Fl[c]) * a.ih[D];
 }
 
+// ---- the flux pass in two kernels.  x and y faces: 16 x 16 column tiles, one plane per
+// workgroup, stencils read directly (the caches serve the reuse; staging the plane with
+// its halo in LDS measured slower); they write (0 + x part) + y part.  z faces: one
+// thread per column marching through a chunk of planes with the six planes k-2 .. k+3 of
+// q and the four gradient fields of the z faces in registers (the next plane loads one
+// step ahead), one face per step, the lower one carried; it adds the z part in place.
+// The sums are formed in the order x, y, z.
+constexpr int FTX = 16, FTY = 16;
+
 template <typename Real, int LAW>
-__global__ void __launch_bounds__(256) visc6_flux_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
-                                                         const Real* __restrict__ G, Real* __restrict__ Rv)
+__global__ void __launch_bounds__(256) visc6_flux_xy_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+                                                            const Real* __restrict__ G, Real* __restrict__ Rv,
+                                                            const int tiles_x)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.ncell) return;
-    const int i = (int)(t % a.nx);
-    const long long r = t / a.nx;
-    const int j = (int)(r % a.ny), k = (int)(r / a.ny);
+    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
+    const int i = (int)(blockIdx.x % tiles_x) * FTX + tx, j = (int)(blockIdx.x / tiles_x) * FTY + ty;
+    const int k = (int)blockIdx.y;
+    if (i >= a.nx || j >= a.ny) return;
     const int px = a.nx + 6, py = a.ny + 6;
     const long long tp = ((long long)(k + 3) * py + (j + 3)) * px + (i + 3);
     Real acc[4] = {0, 0, 0, 0};
     direction6<Real, 0, LAW>(a, Q, G, tp, 1, acc);
     direction6<Real, 1, LAW>(a, Q, G, tp, px, acc);
-    direction6<Real, 2, LAW>(a, Q, G, tp, (long long)px * py, acc);
+    const long long t = ((long long)k * a.ny + j) * a.nx + i;
 #pragma unroll
     for (int c = 0; c < 4; c++) Rv[c * a.ncell + t] = acc[c];
+}
+
+// the z face between window planes 2 and 3 from planes 0 .. 5 (q: 0 .. 3; gradient
+// fields du_z/dx, du_z/dy, du_x/dx, du_y/dy: 4 .. 7), as the upper face of direction6
+template <typename Real, int LAW>
+__device__ __forceinline__ void zface6(const Visc6Args<Real>& a, const Real (*w)[8], Real* F)
+{
+    Real vf[3], dn[4], th, t[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        Real v[6];
+#pragma unroll
+        for (int o = 0; o < 6; o++) v[o] = w[o][c];
+        dn[c] = dface6(v, a.ih[2]);
+        if (c < 3) vf[c] = ifc6(v);
+        else th = ifc6(v);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        Real v[6];
+#pragma unroll
+        for (int o = 0; o < 6; o++) v[o] = w[o][4 + f];
+        t[f] = ifc6(v);
+    }
+    face6<Real, 2, LAW>(a, vf, dn, th, t[0], t[1], t[2], t[3], F);
+}
+
+template <typename Real, int LAW>
+__global__ void __launch_bounds__(256) visc6_flux_z_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+                                                           const Real* __restrict__ G, Real* __restrict__ Rv,
+                                                           const int zchunk)
+{
+    const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ncol = (long long)a.nx * a.ny;
+    if (col >= ncol) return;
+    const int i = (int)(col % a.nx), j = (int)(col / a.nx);
+    const int z0 = (int)blockIdx.y * zchunk, z1 = min(z0 + zchunk, a.nz);
+    const int px = a.nx + 6, py = a.ny + 6;
+    const long long pz = (long long)px * py;
+    const long long p0 = (long long)(j + 3) * px + (i + 3);  // padded offset within a plane
+    constexpr int GZ[4] = {6, 7, 0, 4};                      // du_z/dx, du_z/dy, du_x/dx, du_y/dy
+    auto load = [&](int z, Real* v) {
+        const long long p = (long long)(z + 3) * pz + p0;
+#pragma unroll
+        for (int c = 0; c < 4; c++) v[c] = Q[c * a.npad + p];
+#pragma unroll
+        for (int f = 0; f < 4; f++) v[4 + f] = G[GZ[f] * a.npad + p];
+    };
+    Real w[6][8], nxt[8];
+#pragma unroll
+    for (int p = 0; p < 6; p++) load(z0 - 3 + p, w[p]);  // planes z0-3 .. z0+2
+    Real Fl[4];
+    zface6<Real, LAW>(a, w, Fl);                         // the face below z0
+    load(z0 + 3, nxt);
+    for (int k = z0; k < z1; k++) {
+#pragma unroll
+        for (int p = 0; p < 5; p++)
+#pragma unroll
+            for (int f = 0; f < 8; f++) w[p][f] = w[p + 1][f];
+#pragma unroll
+        for (int f = 0; f < 8; f++) w[5][f] = nxt[f];
+        if (k + 1 < z1) load(k + 4, nxt);  // planes up to z1+2, inside the padded box
+        Real Fu[4];
+        zface6<Real, LAW>(a, w, Fu);
+        const long long t = (long long)k * ncol + col;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            Rv[c * a.ncell + t] += (Fu[c] - Fl[c]) * a.ih[2];
+            Fl[c] = Fu[c];
+        }
+    }
 }
 
 }  // namespace
@@ -244,13 +327,24 @@ hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* 
     hipLaunchKernelGGL((visc6_grad_kernel<Real, 2>), dim3((a.nz + LEN - 1) / LEN, (a.nx + 6 + LNS - 1) / LNS, a.ny + 6),
                        dim3(NTT), 0, st, a, (const Real*)Q, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const unsigned bc = (unsigned)((a.ncell + NTT - 1) / NTT);
-    if (a.vl.law == 0)
-        hipLaunchKernelGGL((visc6_flux_kernel<Real, 0>), dim3(bc), dim3(NTT), 0, st, a, (const Real*)Q,
-                           (const Real*)G, Rv);
-    else
-        hipLaunchKernelGGL((visc6_flux_kernel<Real, 1>), dim3(bc), dim3(NTT), 0, st, a, (const Real*)Q,
-                           (const Real*)G, Rv);
+    // fluxes: x and y faces per plane of 16 x 16 tiles, then the z faces marching through
+    // chunks of about 32 planes
+    const int tiles_x = (a.nx + FTX - 1) / FTX, tiles_y = (a.ny + FTY - 1) / FTY;
+    const int zchunk = std::min(a.nz, 32), nchunks = (a.nz + zchunk - 1) / zchunk;
+    const unsigned ncb = (unsigned)(((long long)a.nx * a.ny + NTT - 1) / NTT);
+    if (a.vl.law == 0) {
+        hipLaunchKernelGGL((visc6_flux_xy_kernel<Real, 0>), dim3(tiles_x * tiles_y, a.nz), dim3(NTT), 0, st, a,
+                           (const Real*)Q, (const Real*)G, Rv, tiles_x);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((visc6_flux_z_kernel<Real, 0>), dim3(ncb, nchunks), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv, zchunk);
+    } else {
+        hipLaunchKernelGGL((visc6_flux_xy_kernel<Real, 1>), dim3(tiles_x * tiles_y, a.nz), dim3(NTT), 0, st, a,
+                           (const Real*)Q, (const Real*)G, Rv, tiles_x);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((visc6_flux_z_kernel<Real, 1>), dim3(ncb, nchunks), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv, zchunk);
+    }
     return hipGetLastError();
 }
 
