@@ -21,9 +21,8 @@
 //      with the constant-Prandtl conductivity; then their divergence.
 // Pass 2 runs once per axis on line tiles staged in LDS (16 lines of 32 cells
 // plus the 3-cell halo), so that each value is read from memory about once per
-// axis.  Pass 3 is two kernels: the x and y faces of 16 x 16 column tiles read
-// their stencils directly (the caches serving the reuse), and the z faces march
-// through the columns with their stencils in registers.
+// axis.  Pass 3 is two kernels marching along y (with the x faces) and along z,
+// each with the marched axis' stencils in registers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -208,38 +207,21 @@ __device__ __forceinline__ void direction6(const Visc6Args<Real>& a, const Real*
     for (int c = 0; c < 4; c++) acc[c] += (Fu[c] - Fl[c]) * a.ih[D];
 }
 
-// ---- the flux pass in two kernels.  x and y faces: 16 x 16 column tiles, one plane per
-// workgroup, stencils read directly (the caches serve the reuse; staging the plane with
-// its halo in LDS measured slower); they write (0 + x part) + y part.  z faces: one
-// thread per column marching through a chunk of planes with the six planes k-2 .. k+3 of
-// q and the four gradient fields of the z faces in registers (the next plane loads one
-// step ahead), one face per step, the lower one carried; it adds the z part in place.
-// The sums are formed in the order x, y, z.
-constexpr int FTX = 16, FTY = 16;
+// ---- the flux pass in two kernels, each marching along one axis with that axis'
+// stencils in registers: one thread per line, the six cells k-2 .. k+3 of q and of the
+// four gradient fields of the faces normal to the axis in a window (the next cell loads
+// one step ahead), one face per step, the lower one carried.  The first kernel marches
+// along y (lanes along x) and also takes the x faces, whose stencils it reads directly
+// (neighbouring lanes share them through the vector cache); it writes (0 + x part) +
+// y part.  The second marches along z and adds the z part in place.  The sums are
+// formed in the order x, y, z.
+constexpr int MCH = 32;  // cells per marched chunk
 
-template <typename Real, int LAW>
-__global__ void __launch_bounds__(256) visc6_flux_xy_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
-                                                            const Real* __restrict__ G, Real* __restrict__ Rv,
-                                                            const int tiles_x)
-{
-    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
-    const int i = (int)(blockIdx.x % tiles_x) * FTX + tx, j = (int)(blockIdx.x / tiles_x) * FTY + ty;
-    const int k = (int)blockIdx.y;
-    if (i >= a.nx || j >= a.ny) return;
-    const int px = a.nx + 6, py = a.ny + 6;
-    const long long tp = ((long long)(k + 3) * py + (j + 3)) * px + (i + 3);
-    Real acc[4] = {0, 0, 0, 0};
-    direction6<Real, 0, LAW>(a, Q, G, tp, 1, acc);
-    direction6<Real, 1, LAW>(a, Q, G, tp, px, acc);
-    const long long t = ((long long)k * a.ny + j) * a.nx + i;
-#pragma unroll
-    for (int c = 0; c < 4; c++) Rv[c * a.ncell + t] = acc[c];
-}
-
-// the z face between window planes 2 and 3 from planes 0 .. 5 (q: 0 .. 3; gradient
-// fields du_z/dx, du_z/dy, du_x/dx, du_y/dy: 4 .. 7), as the upper face of direction6
-template <typename Real, int LAW>
-__device__ __forceinline__ void zface6(const Visc6Args<Real>& a, const Real (*w)[8], Real* F)
+// the face normal to D between window cells 2 and 3 from cells 0 .. 5 (q: 0 .. 3; the
+// gradient fields du_D/dx_E1, du_D/dx_E2, du_E1/dx_E1, du_E2/dx_E2: 4 .. 7), the same
+// arithmetic as the upper face of direction6
+template <typename Real, int D, int LAW>
+__device__ __forceinline__ void window_face6(const Visc6Args<Real>& a, const Real (*w)[8], Real* F)
 {
     Real vf[3], dn[4], th, t[4];
 #pragma unroll
@@ -247,7 +229,7 @@ __device__ __forceinline__ void zface6(const Visc6Args<Real>& a, const Real (*w)
         Real v[6];
 #pragma unroll
         for (int o = 0; o < 6; o++) v[o] = w[o][c];
-        dn[c] = dface6(v, a.ih[2]);
+        dn[c] = dface6(v, a.ih[D]);
         if (c < 3) vf[c] = ifc6(v);
         else th = ifc6(v);
     }
@@ -258,50 +240,63 @@ __device__ __forceinline__ void zface6(const Visc6Args<Real>& a, const Real (*w)
         for (int o = 0; o < 6; o++) v[o] = w[o][4 + f];
         t[f] = ifc6(v);
     }
-    face6<Real, 2, LAW>(a, vf, dn, th, t[0], t[1], t[2], t[3], F);
+    face6<Real, D, LAW>(a, vf, dn, th, t[0], t[1], t[2], t[3], F);
 }
 
-template <typename Real, int LAW>
-__global__ void __launch_bounds__(256) visc6_flux_z_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
-                                                           const Real* __restrict__ G, Real* __restrict__ Rv,
-                                                           const int zchunk)
+// march along D (1: y, lanes along x, lines over (x, z); 2: z, lanes along x, lines over
+// (x, y)) through chunk blockIdx.y of MCH cells
+template <typename Real, int D, int LAW>
+__global__ void __launch_bounds__(256) visc6_flux_march_kernel(const Visc6Args<Real> a, const Real* __restrict__ Q,
+                                                               const Real* __restrict__ G, Real* __restrict__ Rv)
 {
-    const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long ncol = (long long)a.nx * a.ny;
-    if (col >= ncol) return;
-    const int i = (int)(col % a.nx), j = (int)(col / a.nx);
-    const int z0 = (int)blockIdx.y * zchunk, z1 = min(z0 + zchunk, a.nz);
+    static_assert(D == 1 || D == 2, "march along y or z");
+    constexpr int E1 = (D + 1) % 3, E2 = (D + 2) % 3;
+    constexpr int GF[4] = {3 * D + E1, 3 * D + E2, 3 * E1 + E1, 3 * E2 + E2};
+    const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nd = D == 1 ? a.ny : a.nz, no = D == 1 ? a.nz : a.ny;  // marched axis, other axis
+    if (line >= (long long)a.nx * no) return;
+    const int i = (int)(line % a.nx), o = (int)(line / a.nx);
+    const int c0 = (int)blockIdx.y * MCH, c1 = min(c0 + MCH, nd);
     const int px = a.nx + 6, py = a.ny + 6;
-    const long long pz = (long long)px * py;
-    const long long p0 = (long long)(j + 3) * px + (i + 3);  // padded offset within a plane
-    constexpr int GZ[4] = {6, 7, 0, 4};                      // du_z/dx, du_z/dy, du_x/dx, du_y/dy
-    auto load = [&](int z, Real* v) {
-        const long long p = (long long)(z + 3) * pz + p0;
+    // padded index of the cell at position d along the marched axis
+    const long long sd = D == 1 ? (long long)px : (long long)px * py;
+    const long long base = D == 1 ? ((long long)(o + 3) * py + 3) * px + (i + 3) : (long long)(o + 3) * px + 3 * sd + (i + 3);
+    auto load = [&](int d, Real* v) {
+        const long long p = base + (long long)d * sd;
 #pragma unroll
         for (int c = 0; c < 4; c++) v[c] = Q[c * a.npad + p];
 #pragma unroll
-        for (int f = 0; f < 4; f++) v[4 + f] = G[GZ[f] * a.npad + p];
+        for (int f = 0; f < 4; f++) v[4 + f] = G[GF[f] * a.npad + p];
     };
     Real w[6][8], nxt[8];
 #pragma unroll
-    for (int p = 0; p < 6; p++) load(z0 - 3 + p, w[p]);  // planes z0-3 .. z0+2
+    for (int p = 0; p < 6; p++) load(c0 - 3 + p, w[p]);  // cells c0-3 .. c0+2
     Real Fl[4];
-    zface6<Real, LAW>(a, w, Fl);                         // the face below z0
-    load(z0 + 3, nxt);
-    for (int k = z0; k < z1; k++) {
+    window_face6<Real, D, LAW>(a, w, Fl);                 // the face below c0
+    load(c0 + 3, nxt);
+    for (int d = c0; d < c1; d++) {
 #pragma unroll
         for (int p = 0; p < 5; p++)
 #pragma unroll
             for (int f = 0; f < 8; f++) w[p][f] = w[p + 1][f];
 #pragma unroll
         for (int f = 0; f < 8; f++) w[5][f] = nxt[f];
-        if (k + 1 < z1) load(k + 4, nxt);  // planes up to z1+2, inside the padded box
+        if (d + 1 < c1) load(d + 4, nxt);  // up to c1+2, inside the padded box
+        const int j = D == 1 ? d : o, k = D == 1 ? o : d;
+        const long long t = ((long long)k * a.ny + j) * a.nx + i;
+        Real acc[4];
+        if constexpr (D == 1) {
+            acc[0] = acc[1] = acc[2] = acc[3] = Real(0);
+            direction6<Real, 0, LAW>(a, Q, G, base + (long long)d * sd, 1, acc);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) acc[c] = Rv[c * a.ncell + t];
+        }
         Real Fu[4];
-        zface6<Real, LAW>(a, w, Fu);
-        const long long t = (long long)k * ncol + col;
+        window_face6<Real, D, LAW>(a, w, Fu);
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            Rv[c * a.ncell + t] += (Fu[c] - Fl[c]) * a.ih[2];
+            Rv[c * a.ncell + t] = acc[c] + (Fu[c] - Fl[c]) * a.ih[D];
             Fl[c] = Fu[c];
         }
     }
@@ -327,23 +322,22 @@ hipError_t launch_visc6(const Visc6Args<Real>& a, const Real* U, Real* Q, Real* 
     hipLaunchKernelGGL((visc6_grad_kernel<Real, 2>), dim3((a.nz + LEN - 1) / LEN, (a.nx + 6 + LNS - 1) / LNS, a.ny + 6),
                        dim3(NTT), 0, st, a, (const Real*)Q, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // fluxes: x and y faces per plane of 16 x 16 tiles, then the z faces marching through
-    // chunks of about 32 planes
-    const int tiles_x = (a.nx + FTX - 1) / FTX, tiles_y = (a.ny + FTY - 1) / FTY;
-    const int zchunk = std::min(a.nz, 32), nchunks = (a.nz + zchunk - 1) / zchunk;
-    const unsigned ncb = (unsigned)(((long long)a.nx * a.ny + NTT - 1) / NTT);
+    // fluxes: the march along y with the x faces, then the march along z
+    const unsigned by = (unsigned)(((long long)a.nx * a.nz + NTT - 1) / NTT);
+    const unsigned bz = (unsigned)(((long long)a.nx * a.ny + NTT - 1) / NTT);
+    const unsigned cy = (unsigned)((a.ny + MCH - 1) / MCH), cz = (unsigned)((a.nz + MCH - 1) / MCH);
     if (a.vl.law == 0) {
-        hipLaunchKernelGGL((visc6_flux_xy_kernel<Real, 0>), dim3(tiles_x * tiles_y, a.nz), dim3(NTT), 0, st, a,
-                           (const Real*)Q, (const Real*)G, Rv, tiles_x);
+        hipLaunchKernelGGL((visc6_flux_march_kernel<Real, 1, 0>), dim3(by, cy), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((visc6_flux_z_kernel<Real, 0>), dim3(ncb, nchunks), dim3(NTT), 0, st, a, (const Real*)Q,
-                           (const Real*)G, Rv, zchunk);
+        hipLaunchKernelGGL((visc6_flux_march_kernel<Real, 2, 0>), dim3(bz, cz), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
     } else {
-        hipLaunchKernelGGL((visc6_flux_xy_kernel<Real, 1>), dim3(tiles_x * tiles_y, a.nz), dim3(NTT), 0, st, a,
-                           (const Real*)Q, (const Real*)G, Rv, tiles_x);
+        hipLaunchKernelGGL((visc6_flux_march_kernel<Real, 1, 1>), dim3(by, cy), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((visc6_flux_z_kernel<Real, 1>), dim3(ncb, nchunks), dim3(NTT), 0, st, a, (const Real*)Q,
-                           (const Real*)G, Rv, zchunk);
+        hipLaunchKernelGGL((visc6_flux_march_kernel<Real, 2, 1>), dim3(bz, cz), dim3(NTT), 0, st, a, (const Real*)Q,
+                           (const Real*)G, Rv);
     }
     return hipGetLastError();
 }
