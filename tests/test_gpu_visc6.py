@@ -23,6 +23,8 @@ def cases():
         "ns_tgv24": WL.taylor_green(24, viscous=True, ma=0.3),
         "ns_ragged": WL.smooth_random(19, 13, 10, model=WL.NS, seed=22, bc=MIXED_BC, mu=0.02, prandtl=0.7),
         "ns_thin": WL.smooth_random(21, 3, 5, model=WL.NS, seed=31, bc=MIXED_BC, mu=0.05, prandtl=0.72),
+        # several marched chunks along y (32 + 13) and z (32 + 32 + 6)
+        "ns_chunks": WL.smooth_random(10, 45, 70, model=WL.NS, seed=37, bc=MIXED_BC, mu=0.03, prandtl=0.72),
     }
 
 
