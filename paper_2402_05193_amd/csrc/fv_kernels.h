@@ -29,6 +29,10 @@
 #ifndef FV_EARLY_HALO
 #define FV_EARLY_HALO 1
 #endif
+// five-equation model: x/y partial sums of even planes in LDS, odd planes in registers
+#ifndef FV_DIM_HALF_ACC
+#define FV_DIM_HALF_ACC 1
+#endif
 #ifndef FV_SPLIT_OWN_LOAD
 #define FV_SPLIT_OWN_LOAD 0
 #endif

@@ -119,9 +119,11 @@ struct Tile {
     static constexpr int AZ_SIZE = THINC ? (BX + 2) * (BY + 2) : 0;
     static constexpr int NRING = 2 * BX + 2 * BY + 4;
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
-    // five-equation model keeps them in registers instead (LDS budget)
+    // five-equation model (LDS budget) keeps even planes in one LDS slot and odd planes
+    // in registers, or with FV_DIM_HALF_ACC = 0 both in registers
     static constexpr bool ACC_LDS = MODEL != DIM;
-    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : 0;
+    static constexpr bool ACC_HALF = MODEL == DIM && FV_DIM_HALF_ACC;
+    static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : (ACC_HALF ? NC * NCELL : 0);
     static constexpr size_t bytes()
     {
         return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE + AZ_SIZE);
@@ -139,6 +141,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     constexpr int NC = L::NC, V = L::V, P = L::P;
     constexpr bool VISC = TL::VISC;
     constexpr bool ACC_LDS = TL::ACC_LDS;
+    constexpr bool ACC_HALF = TL::ACC_HALF;
     constexpr int PX = TL::PX, PY = TL::PY;
     constexpr int NT = NTH;
     constexpr int NCELL = BX * BY;
@@ -214,7 +217,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 
     Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
-    Real accA[NC], accB[NC];  // x/y part of R of cells s-2, s-1 (register variant)
+    Real accA[NC], accB[NC];  // x/y part of R of cells s-2, s-1 (registers; ACC_HALF: accA the odd planes')
     Real srcA = 0, srcB = 0;  // DIM: x/y part of sum_d (uh_r - uh_l)/dx_d of cells s-2 and s-1
     Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
     Real uhzl = 0;            // its upwinded normal velocity (DIM)
@@ -530,6 +533,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         const Real* slot = ACC + (s & 1) * NC * NCELL + tid;
 #pragma unroll
                         for (int m = 0; m < NC; m++) r[m] = slot[m * NCELL] - (F[m] - Fzl[m]) * idz;
+                    } else if constexpr (ACC_HALF) {
+                        if (s & 1) {
+#pragma unroll
+                            for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < NC; m++) r[m] = ACC[m * NCELL + tid] - (F[m] - Fzl[m]) * idz;
+                        }
                     } else {
 #pragma unroll
                         for (int m = 0; m < NC; m++) r[m] = accA[m] - (F[m] - Fzl[m]) * idz;
@@ -836,7 +847,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
         }
         // rotate carries
-        if constexpr (!ACC_LDS) {
+        if constexpr (ACC_HALF) {
+            // plane s: odd into the register slot, even into the thread's LDS slot
+            if (s & 1) {
+#pragma unroll
+                for (int m = 0; m < NC; m++) accA[m] = accC[m];
+            } else if (has_cell) {
+#pragma unroll
+                for (int m = 0; m < NC; m++) ACC[m * NCELL + tid] = accC[m];
+            }
+        } else if constexpr (!ACC_LDS) {
 #pragma unroll
             for (int m = 0; m < NC; m++) {
                 accA[m] = accB[m];
