@@ -23,35 +23,6 @@
 #ifndef WAVES_PER_EU_F32
 #define WAVES_PER_EU_F32 3
 #endif
-#ifndef FV_PREFETCH_RK
-#define FV_PREFETCH_RK 0
-#endif
-#ifndef FV_EARLY_HALO
-#define FV_EARLY_HALO 1
-#endif
-// five-equation model: x/y partial sums of even planes in LDS, odd planes in registers
-#ifndef FV_DIM_HALF_ACC
-#define FV_DIM_HALF_ACC 1
-#endif
-#ifndef FV_SPLIT_OWN_LOAD
-#define FV_SPLIT_OWN_LOAD 0
-#endif
-#ifndef FV_ROTATE_TASKS
-#define FV_ROTATE_TASKS 1
-#endif
-// x/y reconstructions distributed over (component, cell) items instead of cells
-#ifndef FV_RECON_ITEMS
-#define FV_RECON_ITEMS 1
-#endif
-#ifndef FV_SKIP_PLANE_BARRIER
-#define FV_SKIP_PLANE_BARRIER 1
-#endif
-#ifndef FV_KERNARG_INPLACE
-#define FV_KERNARG_INPLACE 1
-#endif
-#ifndef FV_RECON_UNROLL
-#define FV_RECON_UNROLL 1
-#endif
 
 namespace fv {
 

@@ -120,9 +120,9 @@ struct Tile {
     static constexpr int NRING = 2 * BX + 2 * BY + 4;
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
     // five-equation model (LDS budget) keeps even planes in one LDS slot and odd planes
-    // in registers, or with FV_DIM_HALF_ACC = 0 both in registers
+    // in registers
     static constexpr bool ACC_LDS = MODEL != DIM;
-    static constexpr bool ACC_HALF = MODEL == DIM && FV_DIM_HALF_ACC;
+    static constexpr bool ACC_HALF = MODEL == DIM;
     static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : (ACC_HALF ? NC * NCELL : 0);
     static constexpr size_t bytes()
     {
@@ -167,7 +167,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     const int tx = tid % BX, ty = has_cell ? tid / BX : 0;
     // task lists have a few tasks more than threads; the wave that takes the
     // remainder rotates with the workgroup so co-resident groups spread it over SIMDs
-    const int rt = FV_ROTATE_TASKS ? (tid + 64 * (bid & 3)) % NT : tid;
+    const int rt = (tid + 64 * (bid & 3)) % NT;
     int b = bid;
     // blocks of one tile column are consecutive; consecutive tiles share an XCD's L2
     const int chunk = b % a.nchunks;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         else
 #pragma unroll
             for (int f = 0; f < NC; f++) raw[f] = Real(1);
-        if (!FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+        cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
         const bool xy = (s >= z0) && (s < z1);
         // THINC also stages plane z1 (the cell above the last z face of the chunk)
         const bool need_plane = xy || (VISC && s >= z0 - 2) || (THINC && s >= z0 - 1 && s <= z1);
@@ -259,17 +259,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
 #pragma unroll
         for (int m = 0; m < NC; m++) accC[m] = 0;
 
-        // U^(k), U^n of the cell finalised in this step (s-2), loaded early
+        // U^(k), U^n of the cell finalised in this step (s-2)
         Real pre_k[NC], pre_n[NC];
-        const bool fin = s >= z0 + 2 && own_valid;
-        if (FV_PREFETCH_RK && fin && a.mode != 0) {
-            const long long q = ((long long)(s - 2) * a.ny + gy) * a.nx + gx;
-#pragma unroll
-            for (int m = 0; m < NC; m++) {
-                pre_k[m] = a.Uk[m * a.ncell + q];
-                pre_n[m] = a.mode >= 2 ? a.Un[m * a.ncell + q] : Real(0);
-            }
-        }
+
 
         if (need_plane) {
             // halo cell of this thread (at most one: NHALO <= NT), loaded before the barrier
@@ -300,7 +292,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     hi = (hh & 1) ? BX : -1;
                     hj = (hh & 2) ? BY : -1;
                 }
-                if (FV_EARLY_HALO) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+                load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
             }
             // viscous: the halo columns of the viscous regions need d/dz of two velocity
             // components at plane s; a pair of threads shares a column, the even one
@@ -348,9 +340,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // barriers already ordered every read of it; after a warm-up step (only the
             // in-plane derivatives read it) a barrier is needed here
             const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
-            if (!FV_SKIP_PLANE_BARRIER || !prev_xy) __syncthreads();
-            if (!FV_EARLY_HALO && has_halo) load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
-            if (FV_SPLIT_OWN_LOAD) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+            if (!prev_xy) __syncthreads();
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
             if (has_cell) stage_w(tx, ty, win[3 + WO]);
             if constexpr (THINC) {
@@ -439,8 +429,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Anew[1] = (wp(6, tx, ty + 1) - wp(6, tx, ty - 1)) * (Real(0.5) * idy);
             }
         }
-
-        if (FV_SPLIT_OWN_LOAD && !need_plane) cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
 
         // ---- z work of the own column (registers only): finalises cell s-2
         if (has_cell && s >= z0) {
@@ -553,7 +541,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         r[P] += a.rvisc[3 * a.ncell + q];
                     }
                     Real unew[NC];
-                    if (!FV_PREFETCH_RK && a.mode != 0) {
+                    if (a.mode != 0) {
 #pragma unroll
                         for (int m = 0; m < NC; m++) {
                             pre_k[m] = a.Uk[m * a.ncell + q];
@@ -599,7 +587,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     const Real* c = &wp(m, f - 3, j);
                     teno6a_pair(c[0], c[1], c[2], c[3], c[4], c[5], weps, FL[it], FR[it]);
                 }
-            } else if constexpr (FV_RECON_ITEMS) {
+            } else {
                 // one item = one component of one cell; consecutive lanes take consecutive cells
                 constexpr int NTX = (BX + 2) * BY;
                 auto item = [&](int it) {
@@ -611,20 +599,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
                     if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
                 };
-#pragma unroll FV_RECON_UNROLL
+#pragma unroll 1
                 for (int it = rt; it < NC * NTX; it += NT) item(it);
-            } else {
-                for (int t = rt; t < (BX + 2) * BY; t += NT) {
-                    const int j = t / (BX + 2), i = t % (BX + 2) - 1;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        Real vm, vp;
-                        weno5z_pair(wp(m, i - 2, j), wp(m, i - 1, j), wp(m, i, j), wp(m, i + 1, j), wp(m, i + 2, j),
-                                    weps, vm, vp);
-                        if (i < BX) FL[m * TL::NFX + j * (BX + 1) + i + 1] = vm;
-                        if (i >= 0) FR[m * TL::NFX + j * (BX + 1) + i] = vp;
-                    }
-                }
             }
             if constexpr (VISC) {
                 // d/dy of u (c = 0) and v (c = 1) on the x-face region
@@ -734,7 +710,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     const Real* c = &wp(m, i, f - 3);
                     teno6a_pair(c[0], c[PX], c[2 * PX], c[3 * PX], c[4 * PX], c[5 * PX], weps, GL[it], GR[it]);
                 }
-            } else if constexpr (FV_RECON_ITEMS) {
+            } else {
+                // one item = one component of one cell; consecutive lanes take consecutive cells
                 constexpr int NTY = BX * (BY + 2);
                 auto item = [&](int it) {
                     const int m = it / NTY, t = it - m * NTY;
@@ -745,20 +722,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
                     if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
                 };
-#pragma unroll FV_RECON_UNROLL
+#pragma unroll 1
                 for (int it = rt; it < NC * NTY; it += NT) item(it);
-            } else {
-                for (int t = rt; t < BX * (BY + 2); t += NT) {
-                    const int i = t % BX, j = t / BX - 1;
-#pragma unroll
-                    for (int m = 0; m < NC; m++) {
-                        Real vm, vp;
-                        weno5z_pair(wp(m, i, j - 2), wp(m, i, j - 1), wp(m, i, j), wp(m, i, j + 1), wp(m, i, j + 2),
-                                    weps, vm, vp);
-                        if (j < BY) GL[m * TL::NFY + (j + 1) * BX + i] = vm;
-                        if (j >= 0) GR[m * TL::NFY + j * BX + i] = vp;
-                    }
-                }
             }
             if constexpr (VISC) {
                 // d/dx of v (c = 0) and u (c = 1) on the y-face region
@@ -913,13 +878,10 @@ template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY
 __global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-#if FV_KERNARG_INPLACE
-    // the argument block read in place from the kernel-argument segment
+    // the argument block read in place from the kernel-argument segment (fewer scalar
+    // registers than a copy)
     const StageArgs<Real>* pa = (const StageArgs<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
     stage_body<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>(*pa, (int)blockIdx.x, smem_raw);
-#else
-    stage_body<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>(a, (int)blockIdx.x, smem_raw);
-#endif
 }
 
 // Many independent problems in one launch: the workgroups of problem r are
