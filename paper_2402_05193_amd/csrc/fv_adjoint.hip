@@ -92,21 +92,23 @@ __global__ void __launch_bounds__(ADJ_THREADS) face_adjoint_kernel(const Adjoint
     const long long lines = a.ncell / n;
     const long long t = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
     if (t >= lines * (n + 1)) return;
-    const int f = (int)(t % (n + 1));  // face f lies between cells f-1 and f of the line
-    const long long line = t / (n + 1);
+    // consecutive threads take consecutive x: along the line for x faces, across the
+    // lines for y and z faces (coalesced loads and accumulations)
+    int f;           // face f lies between cells f-1 and f of the line
     int ci, cj, ck;  // coordinates of the line's cells; the DIR one is set per cell below
     if (DIR == 0) {
+        f = (int)(t % (n + 1));
+        const long long line = t / (n + 1);
         ci = 0;
         cj = (int)(line % a.ny);
         ck = (int)(line / a.ny);
-    } else if (DIR == 1) {
-        ci = (int)(line % a.nx);
-        cj = 0;
-        ck = (int)(line / a.nx);
     } else {
-        ci = (int)(line % a.nx);
-        cj = (int)(line / a.nx);
-        ck = 0;
+        ci = (int)(t % a.nx);
+        const long long r = t / a.nx;
+        f = (int)(r % (n + 1));
+        const int o = (int)(r / (n + 1));
+        cj = DIR == 1 ? 0 : o;
+        ck = DIR == 1 ? o : 0;
     }
     const long long stride = DIR == 0 ? 1 : (DIR == 1 ? (long long)a.nx : (long long)a.nx * a.ny);
     const long long base = ((long long)ck * a.ny + cj) * a.nx + ci;  // cell 0 of the line
