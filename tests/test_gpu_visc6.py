@@ -25,6 +25,9 @@ def cases():
         "ns_thin": WL.smooth_random(21, 3, 5, model=WL.NS, seed=31, bc=MIXED_BC, mu=0.05, prandtl=0.72),
         # several marched chunks along y (32 + 13) and z (32 + 32 + 6)
         "ns_chunks": WL.smooth_random(10, 45, 70, model=WL.NS, seed=37, bc=MIXED_BC, mu=0.03, prandtl=0.72),
+        # one cell along an axis: that axis' stencils see the same cell (derivatives vanish)
+        "ns_flat_y": WL.smooth_random(12, 1, 9, model=WL.NS, seed=41, bc=MIXED_BC, mu=0.04, prandtl=0.72),
+        "ns_line_z": WL.smooth_random(1, 1, 40, model=WL.NS, seed=43, bc=MIXED_BC, mu=0.04, prandtl=0.72),
     }
 
 
