@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark runs on one GPU (--gpus 1); several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -58,7 +58,7 @@ enum fv_status {
     FV_EINVAL = -1,        /* invalid configuration or argument value      */
     FV_ENULL = -2,         /* a required pointer is NULL                    */
     FV_EALIGN = -3,        /* a device pointer is not 16-byte aligned       */
-    FV_EUNSUPPORTED = -4,  /* valid request that this build does not serve  */
+    FV_EUNSUPPORTED = -4,  /* valid request that the library does not serve */
     FV_EHIP = -5,          /* a HIP runtime call or kernel launch failed    */
     FV_EINADMISSIBLE = -6, /* check_state found an inadmissible cell        */
     FV_ENONFINITE = -7     /* check_state found a NaN or Inf                */
