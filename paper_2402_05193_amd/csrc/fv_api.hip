@@ -38,12 +38,16 @@ size_t state_bytes(const fv_config* c)
     return es * (size_t)ncomp_of(c->model) * (size_t)c->nx * (size_t)c->ny * (size_t)c->nz;
 }
 
-// workgroups a stage launch aims at (tile columns x z chunks), FP64; FP32 twice
-// as many (its kernels hold fewer registers, more workgroups fit a CU).
-// Measured at 256^3 (NS, stage ms): FP64 512 / 1024 / 2048 / 4096 workgroups
-// 2.58 / 2.54 / 2.51 / 2.53; FP32 1.85 / 1.68 / 1.39 / 1.36.
+// workgroups a stage launch aims at (tile columns x z chunks), FP64 and FP32 (its
+// kernels hold fewer registers, more workgroups fit a CU).  Measured at 256^3 (NS,
+// stage ms): FP64 512 / 1024 / 2048 / 4096 workgroups 2.58 / 2.54 / 2.51 / 2.53;
+// FP32 (three waves per SIMD) 3072 / 4096 / 6144 / 8192 workgroups 1.41 / 1.36 /
+// 1.36 / 1.36, the Euler and five-equation stages alike within 1 %.
 #ifndef FV_TARGET_WORKGROUPS
 #define FV_TARGET_WORKGROUPS 2048
+#endif
+#ifndef FV_TARGET_WORKGROUPS_F32
+#define FV_TARGET_WORKGROUPS_F32 4096
 #endif
 
 constexpr size_t SCALAR_BYTES = 256;  // dt, inverse-dt max, time accumulator, check words
@@ -181,7 +185,7 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     a.tiles_y = (c->ny + TILE_BY - 1) / TILE_BY;
     // z chunks: enough workgroups to fill 256 CUs several times over
     const long long tiles = (long long)a.tiles_x * a.tiles_y;
-    const long long target = f64 ? FV_TARGET_WORKGROUPS : 2 * FV_TARGET_WORKGROUPS;
+    const long long target = f64 ? FV_TARGET_WORKGROUPS : FV_TARGET_WORKGROUPS_F32;
     int nch = (int)((target + tiles - 1) / tiles);
     if (nch < 1) nch = 1;
     int zc = (c->nz + nch - 1) / nch;
