@@ -162,6 +162,29 @@ def test_uniform_state_exactly_preserved():
             assert int(torch.count_nonzero(R)) == 0, (model, bc)
 
 
+def test_large_grid_component_offsets():
+    """Element offsets beyond 2^31 (1024 x 1024 x 416 cells, five FP64 components,
+    17 GB per state): a uniform state with distinct component values gives R = 0
+    exactly and a first RK stage that returns the state bit for bit (a component
+    read from the wrong offset would break the uniformity)."""
+    small = WL.uniform(2, 2, 2, model=WL.NS, state=(1.3, 0.3, -0.2, 0.1, 2.0), mu=0.01)
+    u0 = O.prim_to_cons(oracle_cfg(small), small.W)[:, 0, 0, 0]
+    sc = solver_cfg(small, nx=1024, ny=1024, nz=416)
+    assert sc.ncells * sc.ncomp > 2 ** 31
+    print(f"[parity] large grid {sc.nx}x{sc.ny}x{sc.nz}", flush=True)
+    U = torch.empty((sc.ncomp, sc.nz, sc.ny, sc.nx), dtype=torch.float64, device="cuda")
+    for m in range(sc.ncomp):
+        U[m].fill_(float(u0[m]))
+    R = torch.empty_like(U)
+    S.rhs(sc, U, R, dt=1e-3)
+    assert int(torch.count_nonzero(R)) == 0
+    del R
+    U1 = torch.empty_like(U)
+    S.rk3_stage(sc, 1, U, U, U1, 1e-3)
+    assert torch.equal(U1, U)
+    del U, U1
+    torch.cuda.empty_cache()
+
 def test_conservation_on_gpu():
     for model, extra in [(WL.EULER, {}), (WL.NS, dict(mu=0.01)), (WL.DIM, dict(gamma1=1.66))]:
         case = WL.smooth_random(37, 29, 21, model=model, seed=31, **extra)
