@@ -11,12 +11,20 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvrk3.so")
-# (source, defines): the stage kernels compile per precision and model so that
-# the units build in parallel
-UNITS = [("fv_stage_inst.hip", (f"-DFV_REAL={r}", f"-DFV_MODEL={m}"))
-         for r in ("double", "float") for m in ("NS", "EULER", "DIM")] + [
-    ("fv_stage_launch.hip", ()), ("fv_visc6.hip", ()), ("fv_aux.hip", ()), ("fv_adjoint.hip", ()),
-    ("fv_api.hip", ())]
+# (source, defines, extra options): the stage kernels compile per precision, model and
+# reconstruction (0 primitive WENO5-Z, 1 characteristic WENO5-Z, 2 primitive TENO6-A,
+# 3 characteristic TENO6-A) so that the units build in parallel and each family gets
+# its own code-generation options
+# The iterative occupancy-driven instruction scheduler: measured faster for the
+# primitive WENO5-Z kernels of the single-phase models (NS 256^3 FP64 2.40 -> 2.34 ms
+# per stage, FP32 1.36 -> 1.32, Euler 1.76 -> 1.73, with sixth-order viscous fluxes
+# 3.96 -> 3.80), slower for the characteristic ones (3.01 -> 3.81 ms) and the
+# five-equation model (0.92 -> 0.95 ms), equal for TENO6-A.
+SCHED_OCC = ("-mllvm", "-amdgpu-sched-strategy=iterative-maxocc")
+UNITS = [("fv_stage_inst.hip", (f"-DFV_REAL={r}", f"-DFV_MODEL={m}", f"-DFV_REC={rec}"),
+          SCHED_OCC if (m != "DIM" and rec == 0) else ())
+         for r in ("double", "float") for m in ("NS", "EULER", "DIM") for rec in range(4)] + [
+    (src, (), ()) for src in ("fv_stage_launch.hip", "fv_visc6.hip", "fv_aux.hip", "fv_adjoint.hip", "fv_api.hip")]
 SOURCES = sorted({u[0] for u in UNITS})
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -44,10 +52,10 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
     os.makedirs(objdir, exist_ok=True)
     jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 8))
     cmds = []
-    for src, defs in UNITS:
+    for src, defs, opts in UNITS:
         tag = "".join(d.split("=")[1][0].lower() for d in defs)
         obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
-        cmds.append((obj, [HIPCC, *FLAGS, *(extra or []), *defs, "-c", os.path.join(CSRC, src), "-o", obj]))
+        cmds.append((obj, [HIPCC, *FLAGS, *opts, *(extra or []), *defs, "-c", os.path.join(CSRC, src), "-o", obj]))
     pending = list(cmds)
     running = []
     failed = []

@@ -929,15 +929,25 @@ static hipError_t launch_pos(const StageArgs<Real>& args, const LaunchGeom& g, h
     return launch_tile<Real, MODEL, false, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
-template <typename Real, int MODEL, int VMODE>
-static hipError_t launch_variant(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
+// every variant of one precision, model and reconstruction (explicitly instantiated
+// per reconstruction in fv_stage_inst.hip, so that the families compile separately and
+// each with its own code-generation options)
+template <typename Real, int MODEL, int REC>
+hipError_t launch_rec(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    switch (args.recon) {
-    case REC_WENO_CHAR: return launch_pos<Real, MODEL, REC_WENO_CHAR, VMODE>(args, g, st);
-    case REC_TENO_PRIM: return launch_pos<Real, MODEL, REC_TENO_PRIM, VMODE>(args, g, st);
-    case REC_TENO_CHAR: return launch_pos<Real, MODEL, REC_TENO_CHAR, VMODE>(args, g, st);
-    default: return launch_pos<Real, MODEL, REC_WENO_PRIM, VMODE>(args, g, st);
+    // a viscosity law is a separate instantiation (viscous model only): the law's
+    // pow() must not weigh on the constant-viscosity kernel; sixth-order viscous
+    // fluxes come from separate passes (the stage adds them)
+    if constexpr (MODEL == NS) {
+        if (args.rvisc)
+            return args.vl.law != 0 ? launch_pos<Real, MODEL, REC, VM_EXT_LAW>(args, g, st)
+                                    : launch_pos<Real, MODEL, REC, VM_EXT>(args, g, st);
+        if (args.vl.law != 0) return launch_pos<Real, MODEL, REC, VM_LAW>(args, g, st);
     }
+    if constexpr (MODEL == DIM) {
+        if (args.thinc) return launch_pos<Real, MODEL, REC, XM_THINC>(args, g, st);
+    }
+    return launch_pos<Real, MODEL, REC, VM_CONST>(args, g, st);
 }
 
 template <typename Real, int MODEL>
@@ -946,23 +956,15 @@ size_t stage_lds_bytes()
     return Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>::bytes();
 }
 
-// every variant of one precision and model (explicitly instantiated in fv_stage_inst.hip)
 template <typename Real, int MODEL>
 hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    // a viscosity law is a separate instantiation (viscous model only): the law's
-    // pow() must not weigh on the constant-viscosity kernel; sixth-order viscous
-    // fluxes come from separate passes (the stage adds them)
-    if constexpr (MODEL == NS) {
-        if (args.rvisc)
-            return args.vl.law != 0 ? launch_variant<Real, MODEL, VM_EXT_LAW>(args, g, st)
-                                    : launch_variant<Real, MODEL, VM_EXT>(args, g, st);
-        if (args.vl.law != 0) return launch_variant<Real, MODEL, VM_LAW>(args, g, st);
+    switch (args.recon) {
+    case REC_WENO_CHAR: return launch_rec<Real, MODEL, REC_WENO_CHAR>(args, g, st);
+    case REC_TENO_PRIM: return launch_rec<Real, MODEL, REC_TENO_PRIM>(args, g, st);
+    case REC_TENO_CHAR: return launch_rec<Real, MODEL, REC_TENO_CHAR>(args, g, st);
+    default: return launch_rec<Real, MODEL, REC_WENO_PRIM>(args, g, st);
     }
-    if constexpr (MODEL == DIM) {
-        if (args.thinc) return launch_variant<Real, MODEL, XM_THINC>(args, g, st);
-    }
-    return launch_variant<Real, MODEL, VM_CONST>(args, g, st);
 }
 
 template <typename Real, int MODEL, bool POS>

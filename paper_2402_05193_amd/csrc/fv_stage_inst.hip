@@ -1,12 +1,12 @@
-// fv_stage_inst.hip -- the stage kernels of one precision and model (every
-// limiter, reconstruction and viscosity-law variant), compiled once per
-// (FV_REAL, FV_MODEL) pair given on the command line.
+// fv_stage_inst.hip -- the stage kernels of one precision, model and
+// reconstruction (every limiter and viscosity variant), compiled once per
+// (FV_REAL, FV_MODEL, FV_REC) triple given on the command line.
 #include "fv_stage.h"
 
-#if !defined(FV_REAL) || !defined(FV_MODEL)
-#error "compile with -DFV_REAL=double|float -DFV_MODEL=EULER|NS|DIM"
+#if !defined(FV_REAL) || !defined(FV_MODEL) || !defined(FV_REC)
+#error "compile with -DFV_REAL=double|float -DFV_MODEL=EULER|NS|DIM -DFV_REC=0..3"
 #endif
 
 namespace fv {
-template hipError_t launch_model<FV_REAL, FV_MODEL>(const StageArgs<FV_REAL>&, const LaunchGeom&, hipStream_t);
+template hipError_t launch_rec<FV_REAL, FV_MODEL, FV_REC>(const StageArgs<FV_REAL>&, const LaunchGeom&, hipStream_t);
 }  // namespace fv

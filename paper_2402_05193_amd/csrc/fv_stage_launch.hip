@@ -5,15 +5,18 @@
 namespace fv {
 
 // the kernel families live in fv_stage_inst.hip objects
-#define FV_EXTERN_MODEL(R, M) \
-    extern template hipError_t launch_model<R, M>(const StageArgs<R>&, const LaunchGeom&, hipStream_t);
-FV_EXTERN_MODEL(double, EULER)
-FV_EXTERN_MODEL(double, NS)
-FV_EXTERN_MODEL(double, DIM)
-FV_EXTERN_MODEL(float, EULER)
-FV_EXTERN_MODEL(float, NS)
-FV_EXTERN_MODEL(float, DIM)
-#undef FV_EXTERN_MODEL
+#define FV_EXTERN_REC(R, M)                                                                                    \
+    extern template hipError_t launch_rec<R, M, REC_WENO_PRIM>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
+    extern template hipError_t launch_rec<R, M, REC_WENO_CHAR>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
+    extern template hipError_t launch_rec<R, M, REC_TENO_PRIM>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
+    extern template hipError_t launch_rec<R, M, REC_TENO_CHAR>(const StageArgs<R>&, const LaunchGeom&, hipStream_t);
+FV_EXTERN_REC(double, EULER)
+FV_EXTERN_REC(double, NS)
+FV_EXTERN_REC(double, DIM)
+FV_EXTERN_REC(float, EULER)
+FV_EXTERN_REC(float, NS)
+FV_EXTERN_REC(float, DIM)
+#undef FV_EXTERN_REC
 
 template hipError_t launch_batch_stage<double>(int, bool, const StageArgs<double>*, const int*, int, int, hipStream_t);
 template hipError_t launch_batch_stage<float>(int, bool, const StageArgs<float>*, const int*, int, int, hipStream_t);
