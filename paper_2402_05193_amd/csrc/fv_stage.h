@@ -48,6 +48,33 @@ __device__ __forceinline__ void load_cell(const StageArgs<Real>& a, const Real* 
     if (fz) u[V + 2] = -u[V + 2];
 }
 
+// The same load without the reflections: returns which velocity components to
+// negate (bit 0: x, 1: y, 2: z), so that the caller can apply them after its other
+// loads are issued (a negation right after a load waits for that load)
+template <typename Real>
+__device__ __forceinline__ int load_cell_raw(const StageArgs<Real>& a, const Real* __restrict__ U, int gi, int gj,
+                                             int gk, Real* u, int nc, bool interior_xy)
+{
+    bool fx = false, fy = false, fz = false;
+    int i = gi, j = gj;
+    if (!interior_xy) {
+        i = map_index(gi, a.nx, a.bc[0], a.bc[1], fx);
+        j = map_index(gj, a.ny, a.bc[2], a.bc[3], fy);
+    }
+    const int k = map_index(gk, a.nz, a.bc[4], a.bc[5], fz);
+    const long long q = ((long long)k * a.ny + j) * a.nx + i;
+    for (int m = 0; m < nc; m++) u[m] = U[m * a.ncell + q];
+    return (fx ? 1 : 0) | (fy ? 2 : 0) | (fz ? 4 : 0);
+}
+
+template <typename Real>
+__device__ __forceinline__ void apply_reflections(Real* u, int V, int mask)
+{
+    if (mask & 1) u[V] = -u[V];
+    if (mask & 2) u[V + 1] = -u[V + 1];
+    if (mask & 4) u[V + 2] = -u[V + 2];
+}
+
 // Write R (mode 0) or the Shu-Osher stage combination of cell q (modes 1..3)
 // from the preloaded U^(k) (uk) and U^n (un) of the cell; the written values
 // are returned in `out` for the optional CFL reduction.
@@ -242,13 +269,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     const Real lamz = Real(2 * a.ndim) * dt * idz;
 
     for (int s = s_begin; s <= z1 + 1; s++) {
-        // own column, plane s+2: issued now, converted after the barrier below
+        // own column, plane s+2: issued now, converted once the halo loads are issued
         Real raw[NC];
-        if (has_cell) load_cell<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, V, interior_xy);
+        int rrefl = 0;
+        if (has_cell) rrefl = load_cell_raw<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, interior_xy);
         else
 #pragma unroll
             for (int f = 0; f < NC; f++) raw[f] = Real(1);
-        cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+        auto convert_own = [&]() {
+            apply_reflections(raw, V, rrefl);
+            cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+        };
         const bool xy = (s >= z0) && (s < z1);
         // THINC also stages plane z1 (the cell above the last z face of the chunk)
         const bool need_plane = xy || (VISC && s >= z0 - 2) || (THINC && s >= z0 - 1 && s <= z1);
@@ -267,9 +298,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // halo cell of this thread (at most one: NHALO <= NT), loaded before the barrier
             static_assert(TL::NHALO <= NT, "one halo cell per thread");
             Real vz[2][3];           // viscous halo column: (rho, rho u_a, rho w) at two planes
+            int vrefl = 0;           // negate rho u_a (bit 0), rho w at plane p (bit 1 + p)
             int vc_i = 0, vc_j = 0;  // its tile coordinates
             int hi = 0, hj = 0;
             Real hu[NC];
+            int hrefl = 0;
             const bool has_halo = tid < TL::NHALO;
             if (has_halo) {
                 const int h = tid;
@@ -292,7 +325,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     hi = (hh & 1) ? BX : -1;
                     hj = (hh & 2) ? BY : -1;
                 }
-                load_cell<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, V, interior_xy);
+                hrefl = load_cell_raw<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, interior_xy);
             }
             // viscous: the halo columns of the viscous regions need d/dz of two velocity
             // components at plane s; a pair of threads shares a column, the even one
@@ -326,8 +359,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         const int kk = map_index(s + (odd ? p + 1 : p - 2), a.nz, a.bc[4], a.bc[5], fz);
                         const long long qq = ((long long)kk * a.ny + jj) * a.nx + ii;
                         vz[p][0] = a.Uk[qq];
-                        vz[p][1] = fa ? -a.Uk[ca * a.ncell + qq] : a.Uk[ca * a.ncell + qq];
-                        vz[p][2] = fz ? -a.Uk[(V + 2) * a.ncell + qq] : a.Uk[(V + 2) * a.ncell + qq];
+                        vz[p][1] = a.Uk[ca * a.ncell + qq];
+                        vz[p][2] = a.Uk[(V + 2) * a.ncell + qq];
+                        vrefl |= (fa ? 1 : 0) | (fz ? 2 << p : 0);
                     }
                 } else {
 #pragma unroll
@@ -339,6 +373,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // the plane buffer is overwritten below: after a step with x/y phases their
             // barriers already ordered every read of it; after a warm-up step (only the
             // in-plane derivatives read it) a barrier is needed here
+            convert_own();
             const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
             if (!prev_xy) __syncthreads();
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
@@ -376,6 +411,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
             if (has_halo) {
                 Real w[NC];
+                apply_reflections(hu, V, hrefl);
                 cons_to_prim<Real, MODEL>(mat, hu, w);
                 stage_w(hi, hj, w);
             }
@@ -402,8 +438,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
 #pragma unroll
                     for (int p = 0; p < 2; p++) {
                         const Real ir = rcp(vz[p][0]);
-                        va[p] = vz[p][1] * ir;
-                        vb[p] = vz[p][2] * ir;
+                        va[p] = ((vrefl & 1) ? -vz[p][1] : vz[p][1]) * ir;
+                        vb[p] = ((vrefl & (2 << p)) ? -vz[p][2] : vz[p][2]) * ir;
                     }
                     const Real y0 = __shfl_xor(odd ? va[0] : vb[0], 1, 64);
                     const Real y1 = __shfl_xor(odd ? va[1] : vb[1], 1, 64);
@@ -428,6 +464,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Anew[0] = (wp(6, tx + 1, ty) - wp(6, tx - 1, ty)) * (Real(0.5) * idx);
                 Anew[1] = (wp(6, tx, ty + 1) - wp(6, tx, ty - 1)) * (Real(0.5) * idy);
             }
+        } else {
+            convert_own();
         }
 
         // ---- z work of the own column (registers only): finalises cell s-2
