@@ -373,6 +373,35 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // the plane buffer is overwritten below: after a step with x/y phases their
             // barriers already ordered every read of it; after a warm-up step (only the
             // in-plane derivatives read it) a barrier is needed here
+            // THINC: alpha of the 1-cell ring at planes s-1 and s+1 for d(alpha)/dz at
+            // plane s (highest-numbered threads), issued with the step's other loads
+            Real ring_am = 0, ring_ap = 0;
+            int ring_i = 0, ring_j = 0;
+            if constexpr (THINC) {
+                const int h = NT - 1 - tid;
+                if (h < TL::NRING) {
+                    if (h < 2 * BY) {
+                        ring_j = h >> 1;
+                        ring_i = (h & 1) ? BX : -1;
+                    } else if (h < 2 * BY + 2 * BX) {
+                        const int hh = h - 2 * BY;
+                        ring_i = hh >> 1;
+                        ring_j = (hh & 1) ? BY : -1;
+                    } else {
+                        const int hh = h - 2 * BY - 2 * BX;
+                        ring_i = (hh & 1) ? BX : -1;
+                        ring_j = (hh & 2) ? BY : -1;
+                    }
+                    bool fx = false, fy = false, fz = false;
+                    const int ii = map_index(x0 + ring_i, a.nx, a.bc[0], a.bc[1], fx);
+                    const int jj = map_index(y0 + ring_j, a.ny, a.bc[2], a.bc[3], fy);
+                    const int km = map_index(s - 1, a.nz, a.bc[4], a.bc[5], fz);
+                    const int kp = map_index(s + 1, a.nz, a.bc[4], a.bc[5], fz);
+                    const long long col = (long long)jj * a.nx + ii, plane = (long long)a.ny * a.nx;
+                    ring_am = a.Uk[6 * a.ncell + km * plane + col];
+                    ring_ap = a.Uk[6 * a.ncell + kp * plane + col];
+                }
+            }
             convert_own();
             const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
             if (!prev_xy) __syncthreads();
@@ -383,31 +412,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 // window, the 1-cell ring from memory (highest-numbered threads)
                 const Real hz = Real(0.5) * idz;
                 if (has_cell) AZ[(ty + 1) * (BX + 2) + tx + 1] = (win[4 + WO][6] - win[2 + WO][6]) * hz;
-                const int h = NT - 1 - tid;
-                if (h < TL::NRING) {
-                    int i, j;
-                    if (h < 2 * BY) {
-                        j = h >> 1;
-                        i = (h & 1) ? BX : -1;
-                    } else if (h < 2 * BY + 2 * BX) {
-                        const int hh = h - 2 * BY;
-                        i = hh >> 1;
-                        j = (hh & 1) ? BY : -1;
-                    } else {
-                        const int hh = h - 2 * BY - 2 * BX;
-                        i = (hh & 1) ? BX : -1;
-                        j = (hh & 2) ? BY : -1;
-                    }
-                    bool fx = false, fy = false, fz = false;
-                    const int ii = map_index(x0 + i, a.nx, a.bc[0], a.bc[1], fx);
-                    const int jj = map_index(y0 + j, a.ny, a.bc[2], a.bc[3], fy);
-                    const int km = map_index(s - 1, a.nz, a.bc[4], a.bc[5], fz);
-                    const int kp = map_index(s + 1, a.nz, a.bc[4], a.bc[5], fz);
-                    const long long col = (long long)jj * a.nx + ii, plane = (long long)a.ny * a.nx;
-                    const Real am = a.Uk[6 * a.ncell + km * plane + col];
-                    const Real ap = a.Uk[6 * a.ncell + kp * plane + col];
-                    AZ[(j + 1) * (BX + 2) + i + 1] = (ap - am) * hz;
-                }
+                if (NT - 1 - tid < TL::NRING) AZ[(ring_j + 1) * (BX + 2) + ring_i + 1] = (ring_ap - ring_am) * hz;
             }
             if (has_halo) {
                 Real w[NC];
