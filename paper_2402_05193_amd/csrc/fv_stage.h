@@ -269,17 +269,24 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     const Real lamz = Real(2 * a.ndim) * dt * idz;
 
     for (int s = s_begin; s <= z1 + 1; s++) {
-        // own column, plane s+2: issued now, converted once the halo loads are issued
+        // own column, plane s+2: for the FP64 single-phase kernels loaded after the step's
+        // other loads are issued (its conversion waits for it and would hold them back),
+        // else at the start of the step (measured faster so); converted after those loads
+        constexpr bool LATE_OWN = MODEL != DIM && sizeof(Real) == 8;
         Real raw[NC];
         int rrefl = 0;
-        if (has_cell) rrefl = load_cell_raw<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, interior_xy);
-        else
+        auto load_own = [&]() {
+            if (has_cell) rrefl = load_cell_raw<Real>(a, a.Uk, gx, gy, s + 2, raw, NC, interior_xy);
+            else
 #pragma unroll
-            for (int f = 0; f < NC; f++) raw[f] = Real(1);
+                for (int f = 0; f < NC; f++) raw[f] = Real(1);
+        };
         auto convert_own = [&]() {
+            if constexpr (LATE_OWN) load_own();
             apply_reflections(raw, V, rrefl);
             cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
         };
+        if constexpr (!LATE_OWN) load_own();
         const bool xy = (s >= z0) && (s < z1);
         // THINC also stages plane z1 (the cell above the last z face of the chunk)
         const bool need_plane = xy || (VISC && s >= z0 - 2) || (THINC && s >= z0 - 1 && s <= z1);
