@@ -7,7 +7,7 @@
  * update that consumes it (Sec. 3.4), for three models:
  *   FV_EULER  single-phase inviscid       (Sec. 2.1, 3.5)
  *   FV_NS     single-phase viscous        (Sec. 2.1 dissipative fluxes, Sec. 2.5)
- *   FV_DIM    five-equation diffuse-interface two-phase model (Sec. 2.3, 3.6)
+ *   FV_DIM    five-equation diffuse-interface two-phase model (Sec. 2.3, 3.7)
  * with WENO5-Z or TENO6-A reconstruction of primitive or characteristic
  * variables, the HLLC flux, 4th-order central viscous fluxes and, optionally
  * (default for FV_DIM), the interpolation and flux positivity limiters of
@@ -140,7 +140,7 @@ int32_t fv_ncomp(const fv_config* cfg);
 int workspace_bytes(const fv_config* cfg, size_t* out);
 
 /* Analytic initial condition at cell centres, written as conservative
- * variables U (compute_initial_condition of the paper's API, Sec. 6.1).
+ * variables U (compute_initial_condition of the paper's API, introduction of Sec. 6).
  * Seeded noise uses splitmix64 keyed by (seed, 3*flat_index + component). */
 int init_state(const fv_config* cfg, int32_t case_id, const double* params, int32_t nparams,
                uint64_t seed, void* U, void* stream);
@@ -151,7 +151,7 @@ int prim_to_cons(const fv_config* cfg, const void* W, void* U, void* stream);
 /* W = L_{U->W}(U). */
 int cons_to_prim(const fv_config* cfg, const void* U, void* W, void* stream);
 
-/* R = R_NSE(U), Eq. (FVD) plus the DIM volume-fraction source (Sec. 3.6).
+/* R = R_NSE(U), Eq. (FVD) plus the DIM volume-fraction source (Sec. 3.7).
  * dt is used only by the flux limiter's admissibility test (ignored when the
  * limiters are off).  U and R must not overlap. */
 int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
@@ -188,7 +188,7 @@ int rk3_step(const fv_config* cfg, void* U, double dt, void* ws, void* stream);
 int compute_dt(const fv_config* cfg, const void* U, double* dt_dev, void* ws, void* stream);
 
 /* Advance nsteps TVD-RK3 steps in place (the feedforward of the paper's API,
- * Sec. 6.1).  dt > 0: fixed step; dt <= 0: CFL step recomputed on the device
+ * introduction of Sec. 6).  dt > 0: fixed step; dt <= 0: CFL step recomputed on the device
  * before every step.  t_inout (host, optional): incremented by the simulated
  * time; the only host synchronisation of this call happens when it is given. */
 int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws,

@@ -131,7 +131,11 @@ def lib():
         L.orc_thinc_faces.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
         L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
-        L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double]
+        L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_hllc_speeds.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_thinc_beta.argtypes = [dp, dp, ctypes.c_int]
+        L.orc_thinc_beta.restype = ctypes.c_double
         L.orc_rk3_stage.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double]
         L.orc_dt.argtypes = [cp, dp, ctypes.c_double]
         L.orc_dt.restype = ctypes.c_double
@@ -213,6 +217,25 @@ def hllc(cfg: Config, d: int, WL, WR):
     return F, float(uh[0])
 
 
+def hllc_speeds(cfg: Config, d: int, WL, WR):
+    """Einfeldt signal speeds (s_L, s_R) the HLLC flux uses at a face normal to d."""
+    WL = _arr(WL)
+    WR = _arr(WR)
+    sl = np.zeros(1)
+    sr = np.zeros(1)
+    c = cfg.c_struct()
+    lib().orc_hllc_speeds(ctypes.byref(c), d, _dp(WL), _dp(WR), _dp(sl), _dp(sr))
+    return float(sl[0]), float(sr[0])
+
+
+def thinc_beta(a6, h, d: int) -> float:
+    """beta_i of THINC along d from the volume fractions of the six face neighbours
+    (-x, +x, -y, +y, -z, +z) and the cell sizes h (Sec. 3.2 and 3.7)."""
+    a6 = _arr(a6, (6,))
+    h = _arr(h, (3,))
+    return lib().orc_thinc_beta(_dp(a6), _dp(h), int(d))
+
+
 def face_counts(cfg: Config):
     c = cfg.c_struct()
     return [lib().orc_face_count(ctypes.byref(c), d) for d in range(3)]
@@ -241,15 +264,19 @@ def rhs(cfg: Config, U, dt: float = 0.0, return_flags: bool = False):
     return R
 
 
-def rhs_cells(cfg: Config, U, cells, dt: float = 0.0) -> np.ndarray:
-    """R at the given flat cell indices, shape [ncomp, len(cells)]."""
+def rhs_cells(cfg: Config, U, cells, dt: float = 0.0, return_flags: bool = False):
+    """R at the given flat cell indices, shape [ncomp, len(cells)]; with
+    return_flags also the limiter decisions of each cell's six faces, shape
+    [len(cells), 6] in the order -x, +x, -y, +y, -z, +z."""
     U = _arr(U, cfg.shape)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.empty((cfg.ncomp, len(cells)))
+    flags = np.zeros((len(cells), 6), dtype=np.uint8) if return_flags else None
+    fptr = flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if return_flags else None
     c = cfg.c_struct()
     lib().orc_rhs_cells(ctypes.byref(c), _dp(U), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                        len(cells), _dp(out), float(dt))
-    return out
+                        len(cells), _dp(out), float(dt), fptr)
+    return (out, flags) if return_flags else out
 
 
 def rk3_stage(cfg: Config, stage: int, Un, Uk, dt: float) -> np.ndarray:

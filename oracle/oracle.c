@@ -14,7 +14,7 @@
  * upwinded normal velocity (Sec. 3.2 step 6, Appendix "HLLC approximate
  * Riemann solver"), flux limiter (Sec. 3.3 item 2), central viscous flux
  * (Sec. 2.1 Eq. dissipative_flux, newtonian_shear_stress), then the flux
- * divergence of Eq. (FVD) plus the volume-fraction source of Sec. 3.6, and
+ * divergence of Eq. (FVD) plus the volume-fraction source of Sec. 3.7, and
  * the TVD-RK3 scheme of Sec. 3.4.
  *
  * Readings where the paper is silent or garbled:
@@ -403,23 +403,34 @@ static double recon_one(const orc_cfg *c, double v0, double v1, double v2, doubl
 /* ------------------------------------------------------------------------ */
 static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
+/* Einfeldt signal speeds of a face normal to d (HLLC appendix):
+ * s^L = min(ubar - cbar, uL - cL), s^R = max(ubar + cbar, uR + cR), with the
+ * Roe-averaged ubar and Einfeldt's cbar (reading of the undefined bars).
+ * Exported for the tests. */
+void orc_hllc_speeds(const orc_cfg *c, int d, const double *WL, const double *WR, double *sL_out, double *sR_out)
+{
+    int v = vel0(c);
+    double rhoL = w_density(c, WL), rhoR = w_density(c, WR);
+    double uL = WL[v + d], uR = WR[v + d];
+    double cL = w_sound(c, WL), cR = w_sound(c, WR);
+    double sqL = sqrt(rhoL), sqR = sqrt(rhoR);
+    double ubar = (sqL * uL + sqR * uR) / (sqL + sqR);
+    double cbar2 = (sqL * cL * cL + sqR * cR * cR) / (sqL + sqR)
+                 + 0.5 * sqL * sqR / ((sqL + sqR) * (sqL + sqR)) * (uR - uL) * (uR - uL);
+    double cbar = sqrt(cbar2);
+    *sL_out = fmin(ubar - cbar, uL - cL);
+    *sR_out = fmax(ubar + cbar, uR + cR);
+}
+
 void orc_hllc(const orc_cfg *c, int d, const double *WL, const double *WR, double *F, double *u_hllc)
 {
     int nc = orc_ncomp(c), v = vel0(c), P = pidx(c);
     double rhoL = w_density(c, WL), rhoR = w_density(c, WR);
     double uL = WL[v + d], uR = WR[v + d];
     double pL = WL[P], pR = WR[P];
-    double cL = w_sound(c, WL), cR = w_sound(c, WR);
 
-    /* Einfeldt: s^L = min(ubar - cbar, uL - cL), s^R = max(ubar + cbar, uR + cR),
-     * with Roe-averaged ubar and Einfeldt's cbar (reading of the undefined bars). */
-    double sqL = sqrt(rhoL), sqR = sqrt(rhoR);
-    double ubar = (sqL * uL + sqR * uR) / (sqL + sqR);
-    double cbar2 = (sqL * cL * cL + sqR * cR * cR) / (sqL + sqR)
-                 + 0.5 * sqL * sqR / ((sqL + sqR) * (sqL + sqR)) * (uR - uL) * (uR - uL);
-    double cbar = sqrt(cbar2);
-    double sL = fmin(ubar - cbar, uL - cL);
-    double sR = fmax(ubar + cbar, uR + cR);
+    double sL, sR;
+    orc_hllc_speeds(c, d, WL, WR, &sL, &sR);
     double sminus = fmin(0.0, sL);
     double splus = fmax(0.0, sR);
 
@@ -814,8 +825,11 @@ void orc_char_matrices(const orc_cfg *c, int d, const double *W, double *K, doub
 /* eps = 1e-4, and alpha monotone through the cell along d) the volume       */
 /* fraction follows (1 + theta tanh(beta_i (xt + x_c))) / 2 over the cell,   */
 /* xt = (x - x_{i-1/2}) / dx in [0, 1], with beta_i = beta |n_d| + 0.01,     */
-/* beta = 1, n = grad alpha / |grad alpha| (second-order central             */
-/* differences), theta = sgn(alpha_{i+1} - alpha_{i-1}).  Readings: the      */
+/* beta = 1, and the interface normal of Sec. 3.7: n = grad psi / |grad psi| */
+/* of the smoothed field psi = alpha^0.1 / (alpha^0.1 + (1 - alpha)^0.1)     */
+/* by second-order central differences (alpha clamped to [0, 1] inside psi,  */
+/* where rounding can leave it a few ulps outside and the power is           */
+/* undefined); theta = sgn(alpha_{i+1} - alpha_{i-1}).  Readings: the        */
 /* printed profile has no theta (it could not follow a decreasing           */
 /* interface) and its centre x_c is left blank; x_c is fixed here by the     */
 /* profile's cell average being alpha_i, which gives in closed form          */
@@ -847,21 +861,42 @@ static int thinc_cell(double am, double a0, double ap)
 
 /* THINC face value of cell (i,j,k) on its face towards side (0: -d, 1: +d); its
  * state W is overwritten in the volume fraction and partial densities */
+/* smoothed volume fraction of the interface normal (Sec. 3.7) */
+static double thinc_psi(double a)
+{
+    a = fmin(1.0, fmax(0.0, a));
+    double p = pow(a, 0.1), q = pow(1.0 - a, 0.1);
+    return p / (p + q);
+}
+
+/* beta_i of a cell along d from the volume fractions of its six face
+ * neighbours a6 = (alpha_{-x}, alpha_{+x}, alpha_{-y}, alpha_{+y}, alpha_{-z},
+ * alpha_{+z}) and the cell sizes h (exported for the tests) */
+double orc_thinc_beta(const double *a6, const double *h, int d)
+{
+    double g[3], gn = 0.0;
+    for (int e = 0; e < 3; e++) {
+        g[e] = (thinc_psi(a6[2 * e + 1]) - thinc_psi(a6[2 * e])) / (2.0 * h[e]);
+        gn += g[e] * g[e];
+    }
+    return THINC_BETA * fabs(g[d]) / sqrt(gn) + 0.01;
+}
+
 static void thinc_state(const orc_cfg *c, const padded *p, int d, int i, int j, int k, int side, double *W)
 {
     double h[3] = {c->dx, c->dy, c->dz};
-    double g[3], gn = 0.0;
+    double a6[6];
     for (int e = 0; e < 3; e++) {
         const int *o = DI[e];
-        g[e] = (get_q(p, 6, i + o[0], j + o[1], k + o[2]) - get_q(p, 6, i - o[0], j - o[1], k - o[2])) / (2.0 * h[e]);
-        gn += g[e] * g[e];
+        a6[2 * e] = get_q(p, 6, i - o[0], j - o[1], k - o[2]);
+        a6[2 * e + 1] = get_q(p, 6, i + o[0], j + o[1], k + o[2]);
     }
     const int *o = DI[d];
     double am = get_q(p, 6, i - o[0], j - o[1], k - o[2]);
     double a0 = get_q(p, 6, i, j, k);
     double ap = get_q(p, 6, i + o[0], j + o[1], k + o[2]);
     double theta = ap > am ? 1.0 : -1.0;
-    double beta = THINC_BETA * fabs(g[d]) / sqrt(gn) + 0.01;
+    double beta = orc_thinc_beta(a6, h, d);
     double f[3];
     orc_thinc_faces(a0, theta, beta, f);
     double rho1 = get_q(p, 0, i, j, k) / a0, rho2 = get_q(p, 1, i, j, k) / (1.0 - a0);
@@ -950,7 +985,7 @@ static void face_flux(const orc_cfg *c, const padded *p, int d, int i, int j, in
 }
 
 /* ------------------------------------------------------------------------ */
-/* R_NSE (Eq. FVD) plus the DIM source (Sec. 3.6).                           */
+/* R_NSE (Eq. FVD) plus the DIM source (Sec. 3.7).                           */
 /* flags_out (optional): per direction d an array of (n_d+1) * (others)     */
 /* face decision bytes, laid out [d][k][j][i] with the face index fastest   */
 /* along d; face index f sits between cells f-1 and f.                      */
@@ -1019,9 +1054,11 @@ void orc_rhs(const orc_cfg *c, const double *U, double *R, double dt, uint8_t *f
 }
 
 /* R at a list of cells, each evaluated independently from a local padded
- * neighbourhood (used to check very large grids at sampled cells). */
+ * neighbourhood (used to check very large grids at sampled cells).
+ * flags_out (optional): 6 decision bytes per cell, the faces -x, +x, -y, +y,
+ * -z, +z in that order, bits as in face_flux. */
 void orc_rhs_cells(const orc_cfg *c, const double *U, const int64_t *cells, int64_t ncell, double *Rout,
-                   double dt)
+                   double dt, uint8_t *flags_out)
 {
     int nc = orc_ncomp(c);
     long n = ncells(c);
@@ -1061,9 +1098,13 @@ void orc_rhs_cells(const orc_cfg *c, const double *U, const int64_t *cells, int6
         for (int d = 0; d < 3; d++) {
             const int *o = DI[d];
             double Fl[MAXC], Fr[MAXC], uhl, uhr;
-            int fl;
-            face_flux(c, &p, d, -o[0], -o[1], -o[2], dt, Fl, &uhl, &fl);
-            face_flux(c, &p, d, 0, 0, 0, dt, Fr, &uhr, &fl);
+            int fll, flr;
+            face_flux(c, &p, d, -o[0], -o[1], -o[2], dt, Fl, &uhl, &fll);
+            face_flux(c, &p, d, 0, 0, 0, dt, Fr, &uhr, &flr);
+            if (flags_out) {
+                flags_out[6 * s + 2 * d] = (uint8_t)fll;
+                flags_out[6 * s + 2 * d + 1] = (uint8_t)flr;
+            }
             for (int m = 0; m < nc; m++) acc[m] -= (Fr[m] - Fl[m]) / h[d];
             src += (uhr - uhl) / h[d];
         }

@@ -4,7 +4,7 @@
 // so that the instantiations compile in parallel.
 //
 // One kernel evaluates R_NSE (arXiv:2402.05193 Eq. (FVD), plus the volume
-// fraction source of Sec. 3.6) for a block of cells and applies one Shu-Osher
+// fraction source of Sec. 3.7) for a block of cells and applies one Shu-Osher
 // stage (Sec. 3.4) -- or writes R itself.  Face states and fluxes never
 // leave the chip.
 //

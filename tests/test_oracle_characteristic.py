@@ -43,7 +43,7 @@ def flux_jacobian(cfg, d, W, h=1e-6):
         dU[:, q] = (U_of(W + e) - U_of(W - e)) / (2 * e[q])
         dF[:, q] = (F_of(W + e) - F_of(W - e)) / (2 * e[q])
     if cfg.model == O.DIM:
-        # the volume-fraction equation carries the source alpha1 div(u) (Sec. 3.6): its
+        # the volume-fraction equation carries the source alpha1 div(u) (Sec. 3.7): its
         # quasi-linear coefficient is u_n on alpha1 only, not d(alpha1 u_n)/dW
         dF[6, 2 + d] -= W[6]
     return np.linalg.solve(dU, dF)

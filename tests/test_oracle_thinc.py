@@ -93,3 +93,39 @@ def test_same_operator_along_every_axis(axis):
     perm = [0, 1, 2, 3, 4, 5, 6]
     perm[2], perm[2 + axis] = perm[2 + axis], perm[2]
     assert np.abs(Ra[perm].ravel() - R.ravel()).max() <= 1e-12 * np.abs(R).max()
+
+
+def alpha_of_psi_ratio(k):
+    """Volume fraction whose smoothed value psi = a^0.1 / (a^0.1 + (1 - a)^0.1) is
+    exactly 1 / (1 + k): a = 1 / (1 + k^10)."""
+    return 1.0 / (1.0 + k ** 10)
+
+
+@pytest.mark.parametrize("hx,hy", [(1.0, 1.0), (2.0, 1.0)])
+def test_interface_normal_from_smoothed_volume_fraction(hx, hy):
+    """Sec. 3.7: the THINC normal is grad psi / |grad psi| of the smoothed volume
+    fraction, by central differences.  Neighbours chosen so that psi is a simple
+    fraction: psi = 1/3, 2/3 along x, 1/4, 1/2 along y, equal along z, so
+    grad psi = (1/(6 hx), 1/(8 hy), 0) and beta_d = |n_d| + 0.01 in closed form
+    (0.81, 0.61 on a square grid: a 3-4-5 triangle).  The gradient of alpha
+    itself points elsewhere (n_x = 0.894 on the square grid)."""
+    a6 = [alpha_of_psi_ratio(2.0), alpha_of_psi_ratio(0.5), alpha_of_psi_ratio(3.0), alpha_of_psi_ratio(1.0),
+          0.3, 0.3]
+    h = [hx, hy, 1.0]
+    gx, gy = 1.0 / (6.0 * hx), 1.0 / (8.0 * hy)
+    nrm = np.hypot(gx, gy)
+    assert O.thinc_beta(a6, h, 0) == pytest.approx(gx / nrm + 0.01, rel=1e-14)
+    assert O.thinc_beta(a6, h, 1) == pytest.approx(gy / nrm + 0.01, rel=1e-14)
+    assert O.thinc_beta(a6, h, 2) == pytest.approx(0.01, rel=1e-14)
+    if hx == hy:
+        assert O.thinc_beta(a6, h, 0) == pytest.approx(0.81, rel=1e-14)
+        ga = np.array([a6[1] - a6[0], a6[3] - a6[2]])
+        assert abs(ga[0] / np.hypot(*ga) + 0.01 - 0.81) > 0.05      # the alpha gradient's answer differs
+
+
+def test_interface_normal_volume_fraction_clamped():
+    """Rounding can leave a neighbour's volume fraction a few ulps outside [0, 1];
+    psi takes the clamped value (0 or 1), so the normal stays finite."""
+    a6 = [-1e-17, 1.0 + 2e-16, 0.5, 0.5, 0.5, 0.5]
+    assert O.thinc_beta(a6, [1.0, 1.0, 1.0], 0) == pytest.approx(1.01, rel=1e-15)
+    assert O.thinc_beta(a6, [1.0, 1.0, 1.0], 1) == pytest.approx(0.01, rel=1e-15)
