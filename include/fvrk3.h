@@ -71,9 +71,21 @@ enum fv_case {
                             params: Ma, rho0, noise amplitude (seeded +-noise on u, v, w)   */
     FV_CASE_RIEMANN = 2, /* planar two-state problem: params: axis, x0 (fraction of the
                             domain along axis), W_left (ncomp), W_right (ncomp)            */
-    FV_CASE_SBI = 3      /* shock-bubble: params: x_shock, x_c, y_c, z_c, radius, eps_alpha,
+    FV_CASE_SBI = 3,     /* shock-bubble: params: x_shock, x_c, y_c, z_c, radius, eps_alpha,
                             W_postshock_air (rho, u, p), W_air (rho, p), rho_bubble;
                             fluid 1 = bubble gas, fluid 2 = air; coordinates in metres     */
+    FV_CASE_GAUSS_WAVE = 4, /* the convergence test's density wave (Sec. 5.1): params: axis,
+                            u, p; rho = 1 + 5 exp(-200 (s - 0.5)^2) + 5 exp(-200 (s - 1.5)^2)
+                            along the axis (s = cell coordinate from 0; [0, 2) with
+                            periodic ends for the paper's test) as exact cell averages,
+                            velocity u along the axis, pressure p; single phase            */
+    FV_CASE_ISENTROPIC_VORTEX = 5 /* Shu's isentropic vortex, z-invariant: params: strength,
+                            x_c, y_c, u_inf, v_inf; rho_inf = p_inf = 1, T = p / rho,
+                            u = u_inf - strength/(2 pi) exp((1 - r^2)/2) (y - y_c),
+                            v = v_inf + strength/(2 pi) exp((1 - r^2)/2) (x - x_c),
+                            T = 1 - (gamma-1) strength^2/(8 gamma pi^2) exp(1 - r^2),
+                            rho = T^(1/(gamma-1)); conservative cell averages by 5 x 5
+                            Gauss-Legendre points; single phase                            */
 };
 
 /* Problem description, passed by pointer to every call and copied into
@@ -139,8 +151,10 @@ int32_t fv_ncomp(const fv_config* cfg);
  * values (each block aligned to 256 bytes). */
 int workspace_bytes(const fv_config* cfg, size_t* out);
 
-/* Analytic initial condition at cell centres, written as conservative
- * variables U (compute_initial_condition of the paper's API, introduction of Sec. 6).
+/* Analytic initial condition written as conservative variables U
+ * (compute_initial_condition of the paper's API, introduction of Sec. 6): values at
+ * cell centres, except the cell averages of FV_CASE_GAUSS_WAVE and
+ * FV_CASE_ISENTROPIC_VORTEX.
  * Seeded noise uses splitmix64 keyed by (seed, 3*flat_index + component). */
 int init_state(const fv_config* cfg, int32_t case_id, const double* params, int32_t nparams,
                uint64_t seed, void* U, void* stream);
@@ -160,6 +174,22 @@ int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
  * visc_order 6, whose viscous passes keep their intermediate fields there;
  * otherwise the same as rhs).  The workspace contents are overwritten. */
 int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, void* stream);
+
+/* Bytes of the limiter decision record of rhs_flags: one byte per cell face,
+ * (nx+1) ny nz + nx (ny+1) nz + nx ny (nz+1). */
+int limiter_flag_bytes(const fv_config* cfg, size_t* out);
+
+/* rhs plus the decisions of the positivity limiters of Sec. 3.3 at every face
+ * (the interpolation limiter's switch of each reconstructed state to its cell
+ * state, item 1, and the flux limiter's switch to the first-order HLLC flux,
+ * item 2).  R is the same as rhs (and rhs_ws) computes.
+ * flags: device buffer of limiter_flag_bytes(cfg) bytes, written in full: the
+ *   x faces first, [k][j][i] with i = 0..nx the face between cells i-1 and i
+ *   (i fastest), then the y faces [k][j = 0..ny][i], then the z faces
+ *   [k = 0..nz][j][i].  Bit 0: the left state was replaced, bit 1: the right
+ *   state, bit 2: the flux limiter tripped.  With the limiters off every byte is 0.
+ * ws: workspace of workspace_bytes(cfg) for visc_order 6 (NULL otherwise). */
+int rhs_flags(const fv_config* cfg, const void* U, void* R, double dt, uint8_t* flags, void* ws, void* stream);
 
 /* One TVD-RK3 stage (Sec. 3.4), the benchmarked unit:
  *   stage 1: Uout = Un + dt R(Un)                        (Uk must equal Un)

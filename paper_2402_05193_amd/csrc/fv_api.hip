@@ -255,12 +255,27 @@ WsLayout ws_layout(const fv_config* c, void* ws)
     return w;
 }
 
+// bytes of the limiter decision record: one per face, x faces then y then z
+void flag_offsets(const fv_config* c, long long off[3], long long* total)
+{
+    const long long nx = c->nx, ny = c->ny, nz = c->nz;
+    off[0] = 0;
+    off[1] = (nx + 1) * ny * nz;
+    off[2] = off[1] + nx * (ny + 1) * nz;
+    *total = off[2] + nx * ny * (nz + 1);
+}
+
 template <typename Real>
 int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt, const double* dt_dev,
-               hipStream_t st, unsigned long long* inv_max, const WsLayout* w)
+               hipStream_t st, unsigned long long* inv_max, const WsLayout* w, unsigned char* flags = nullptr)
 {
     fv::LaunchGeom g;
     fv::StageArgs<Real> a = stage_args<Real>(c, g);
+    if (flags) {
+        long long total;
+        flag_offsets(c, a.flag_off, &total);
+        a.flags = flags;
+    }
     if (visc6(c)) {
         if (!w) return fail(FV_EUNSUPPORTED, "sixth-order viscous fluxes need a workspace");
         fv::Visc6Args<Real> v;
@@ -293,10 +308,10 @@ int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, voi
 
 int stage_dispatch(const fv_config* c, int mode, const void* Un, const void* Uk, void* out, double dt,
                    const double* dt_dev, hipStream_t st, unsigned long long* inv_max = nullptr,
-                   const WsLayout* w = nullptr)
+                   const WsLayout* w = nullptr, unsigned char* flags = nullptr)
 {
-    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w);
-    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w);
+    if (c->dtype == FV_F64) return stage_impl<double>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w, flags);
+    return stage_impl<float>(c, mode, Un, Uk, out, dt, dt_dev, st, inv_max, w, flags);
 }
 
 }  // namespace
@@ -332,13 +347,18 @@ int init_state(const fv_config* cfg, int32_t case_id, const double* params, int3
     case FV_CASE_TGV: need = 3; break;
     case FV_CASE_RIEMANN: need = 2 + 2 * nc; break;
     case FV_CASE_SBI: need = 12; break;
+    case FV_CASE_GAUSS_WAVE: need = 3; break;
+    case FV_CASE_ISENTROPIC_VORTEX: need = 5; break;
     default: return fail(FV_EINVAL, "case_id %d unknown", case_id);
     }
-    if (case_id == FV_CASE_TGV && cfg->model == FV_DIM) return fail(FV_EINVAL, "TGV is a single-phase case");
+    if ((case_id == FV_CASE_TGV || case_id == FV_CASE_GAUSS_WAVE || case_id == FV_CASE_ISENTROPIC_VORTEX) &&
+        cfg->model == FV_DIM)
+        return fail(FV_EINVAL, "case %d is a single-phase case", case_id);
     if (case_id == FV_CASE_SBI && cfg->model != FV_DIM) return fail(FV_EINVAL, "SBI needs the DIM model");
     if (nparams < need) return fail(FV_EINVAL, "case %d needs %d parameters, got %d", case_id, need, nparams);
     if (!params) return fail(FV_ENULL, "params is NULL");
-    if (case_id == FV_CASE_RIEMANN && (params[0] < 0 || params[0] > 2)) return fail(FV_EINVAL, "axis must be 0, 1 or 2");
+    if ((case_id == FV_CASE_RIEMANN || case_id == FV_CASE_GAUSS_WAVE) && (params[0] < 0 || params[0] > 2))
+        return fail(FV_EINVAL, "axis must be 0, 1 or 2");
     const fv::AuxArgs a = aux_args(cfg);
     hipError_t e = cfg->dtype == FV_F64
                        ? fv::launch_init<double>(a, case_id, params, nparams, seed, (double*)U, (hipStream_t)stream)
@@ -391,6 +411,44 @@ int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, vo
     if (!(dt >= 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and >= 0");
     const WsLayout w = ws_layout(cfg, ws);
     return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, (hipStream_t)stream, nullptr, &w);
+}
+
+int limiter_flag_bytes(const fv_config* cfg, size_t* out)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if (!out) return fail(FV_ENULL, "out is NULL");
+    long long off[3], total;
+    flag_offsets(cfg, off, &total);
+    *out = (size_t)total;
+    return FV_OK;
+}
+
+int rhs_flags(const fv_config* cfg, const void* U, void* R, double dt, uint8_t* flags, void* ws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(U, "U")) || (r = check_ptr(R, "R"))) return r;
+    if (!flags) return fail(FV_ENULL, "flags is NULL");
+    if (U == R) return fail(FV_EINVAL, "U and R must not overlap");
+    if (!(dt >= 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    WsLayout w;
+    const WsLayout* wp = nullptr;
+    if (visc6(cfg)) {
+        if ((r = check_ptr(ws, "ws"))) return fail(r, "visc_order 6 needs a workspace");
+        w = ws_layout(cfg, ws);
+        wp = &w;
+    }
+    if (!positivity_on(cfg)) {
+        // no limiter acts: every decision byte is 0
+        long long off[3], total;
+        flag_offsets(cfg, off, &total);
+        hipError_t e = hipMemsetAsync(flags, 0, (size_t)total, st);
+        if (e != hipSuccess) return hip_fail(e, "rhs_flags: clear");
+        return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, st, nullptr, wp);
+    }
+    return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, st, nullptr, wp, flags);
 }
 
 int rk3_stage(const fv_config* cfg, int32_t stage, const void* Un, const void* Uk, void* Uout, double dt,

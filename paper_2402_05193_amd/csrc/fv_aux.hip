@@ -129,6 +129,50 @@ __global__ void __launch_bounds__(AUX_THREADS) init_kernel(const AuxArgs a, cons
         const double c = (idx3[axis] + 0.5) / n3[axis];
         const double* src = c < frac ? &ip.p[2] : &ip.p[2 + NC];
         for (int m = 0; m < NC; m++) w[m] = src[m];
+    } else if (ip.case_id == 4) {  // density wave of two Gaussians (single phase), exact cell averages
+        // rho(s) = 1 + 5 exp(-200 (s - 0.5)^2) + 5 exp(-200 (s - 1.5)^2) along the axis; the
+        // cell average from the antiderivative sqrt(pi)/(2 sqrt(200)) erf(sqrt(200)(s - c))
+        const int axis = (int)ip.p[0];
+        const int idx3[3] = {i, j, k};
+        const double hs[3] = {a.dx, a.dy, a.dz};
+        const double h = hs[axis], s0 = idx3[axis] * h, s1 = s0 + h;
+        const double r = sqrt(200.0);
+        double acc = 0.0;
+        for (int g = 0; g < 2; g++) {
+            const double c = g == 0 ? 0.5 : 1.5;
+            acc += erf(r * (s1 - c)) - erf(r * (s0 - c));
+        }
+        w[0] = 1.0 + 5.0 * sqrt(M_PI) / (2.0 * r) * acc / h;
+        w[V + axis] = ip.p[1];
+        w[P] = ip.p[2];
+    } else if (ip.case_id == 5) {  // isentropic vortex (single phase), z-invariant
+        // cell averages of the conservative variables by 5 x 5 Gauss-Legendre points in x, y
+        const double eps = ip.p[0], xc = ip.p[1], yc = ip.p[2], uinf = ip.p[3], vinf = ip.p[4];
+        const double gamma = a.matd.gamma;
+        const double t1 = sqrt(5.0 - 2.0 * sqrt(10.0 / 7.0)) / 3.0, t2 = sqrt(5.0 + 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+        const double gx[5] = {-t2, -t1, 0.0, t1, t2};
+        const double w1 = (322.0 + 13.0 * sqrt(70.0)) / 900.0, w2 = (322.0 - 13.0 * sqrt(70.0)) / 900.0;
+        const double gw[5] = {w2, w1, 128.0 / 225.0, w1, w2};
+        double uc[NC];
+        for (int m = 0; m < NC; m++) uc[m] = 0.0;
+        for (int ga = 0; ga < 5; ga++)
+            for (int gb = 0; gb < 5; gb++) {
+                const double X = x + 0.5 * gx[ga] * a.dx - xc, Y = y + 0.5 * gx[gb] * a.dy - yc;
+                const double wt = 0.25 * gw[ga] * gw[gb];
+                const double r2 = X * X + Y * Y;
+                const double f = exp(0.5 * (1.0 - r2));
+                const double u = uinf - eps / (2.0 * M_PI) * f * Y, v = vinf + eps / (2.0 * M_PI) * f * X;
+                const double T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * M_PI * M_PI) * exp(1.0 - r2);
+                const double rho = pow(T, 1.0 / (gamma - 1.0));
+                const double p = rho * T;
+                uc[0] += wt * rho;
+                uc[V] += wt * rho * u;
+                uc[V + 1] += wt * rho * v;
+                uc[P] += wt * (p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v));
+            }
+#pragma unroll
+        for (int m = 0; m < NC; m++) U[m * a.ncell + q] = (Real)uc[m];
+        return;
     } else {  // shock-bubble interaction (five-equation model)
         const double xs = ip.p[0], xc = ip.p[1], yc = ip.p[2], zc = ip.p[3], R = ip.p[4], eps = ip.p[5];
         const double rho2 = ip.p[6], u2 = ip.p[7], p2 = ip.p[8], rho_air = ip.p[9], p_air = ip.p[10];

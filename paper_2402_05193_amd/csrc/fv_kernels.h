@@ -69,6 +69,12 @@ struct StageArgs {
     // finalised; null: the stage computes the 4th-order viscous fluxes itself
     const Real* rvisc;
     int thinc;           // five-equation model: THINC volume-fraction faces in interface cells
+    // limiter decisions of every face (null: not recorded; with the limiters on, the
+    // kernel variant that writes them): one byte per face, the x faces at
+    // flags[flag_off[0] + (k ny + j)(nx+1) + i], y at flags[flag_off[1] + (k (ny+1) + j) nx + i],
+    // z at flags[flag_off[2] + (k ny + j) nx + i]
+    unsigned char* flags;
+    long long flag_off[3];
 };
 
 struct LaunchGeom {

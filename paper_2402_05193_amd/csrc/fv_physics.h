@@ -474,12 +474,24 @@ __device__ __forceinline__ void char_face_states(const Material<Real>& mat, Sten
 // (eps = 1e-4) and the volume fraction is monotone through it along the face
 // normal (am, a0, ap).  Its profile over the cell, xt in [0, 1] from its -d
 // face, is (1 + theta tanh(beta (xt + x_c))) / 2 with theta = sgn(ap - am),
-// beta = |n_d| + 0.01 (n = grad alpha / |grad alpha|; g_d and gn2 = |grad|^2 in
-// any common scale) and x_c such that the profile's mean is a0:
+// beta = |n_d| + 0.01 (n = grad psi / |grad psi| of the smoothed volume fraction
+// of Sec. 3.7, see thinc_psi; g_d and gn2 = |grad psi|^2 in any common scale) and
+// x_c such that the profile's mean is a0:
 //   T = tanh(beta x_c) = (exp(theta beta (2 a0 - 1)) - cosh beta) / sinh beta.
 // Face values: (1 + theta T) / 2 at the -d face (side 0) and
 // (1 + theta tanh(beta + beta x_c)) / 2 at the +d face (side 1), the latter
 // from the addition theorem.  Returns false (af untouched) outside interface cells.
+// Smoothed volume fraction from which the interface normal is taken (Sec. 3.7):
+// psi = a^0.1 / (a^0.1 + (1 - a)^0.1), with a clamped to [0, 1] (rounding can
+// leave it a few ulps outside, where the power is undefined).
+template <typename Real>
+__device__ __forceinline__ Real thinc_psi(Real a)
+{
+    a = fmin(Real(1), fmax(Real(0), a));
+    const Real p = pow(a, Real(0.1)), q = pow(Real(1) - a, Real(0.1));
+    return p / (p + q);
+}
+
 template <typename Real>
 __device__ __forceinline__ bool thinc_face(Real am, Real a0, Real ap, Real gd, Real gn2, int side, Real& af)
 {

@@ -129,7 +129,9 @@ struct Tile {
     static constexpr bool THINC = THINC_;  // interface capturing (five-equation model)
     static constexpr int NT = NTH;
     static constexpr int NCELL = BX * BY;
-    static constexpr int NW = NC + (VISC ? 1 : 0);  // primitives (+ T = p/rho) of the LDS plane
+    // primitives of the LDS plane, plus T = p/rho (viscous) or the smoothed volume
+    // fraction psi of the interface normal (THINC)
+    static constexpr int NW = NC + ((VISC || THINC) ? 1 : 0);
     static constexpr int PX = BX + 6, PY = BY + 6;  // plane with 3-cell halo
     static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
     static constexpr int NFMAX = NFX > NFY ? NFX : NFY;
@@ -142,7 +144,7 @@ struct Tile {
     // halo ring of the plane; corners: 2 deep for the viscous cross terms, 1 deep
     // for the volume-fraction gradient of THINC
     static constexpr int NHALO = 6 * BY + 6 * BX + (VISC ? 16 : (THINC ? 4 : 0));
-    // THINC: d(alpha)/dz at the plane for the tile and its 1-cell ring
+    // THINC: d(psi)/dz at the plane for the tile and its 1-cell ring
     static constexpr int AZ_SIZE = THINC ? (BX + 2) * (BY + 2) : 0;
     static constexpr int NRING = 2 * BX + 2 * BY + 4;
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
@@ -158,7 +160,7 @@ struct Tile {
 };
 
 // One workgroup of the fused stage: tile column `bid` of the problem described by `a`.
-template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
+template <typename Real, int MODEL, int POS, int REC, int VMODE, int BX, int BY, int NTH>
 __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int bid, unsigned char* smem_raw)
 {
     using L = Layout<MODEL>;
@@ -174,6 +176,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     constexpr int NCELL = BX * BY;
     constexpr int PLANE = PY * PX;
     static_assert(NT >= NCELL && NT % 64 == 0, "threads must cover the tile");
+    // POS: 0 limiters off, 1 on, 2 on and every face's decisions written to a.flags
+    // (bit 0: interpolation limiter on the left state, bit 1: on the right state,
+    // bit 2: flux limiter), per direction [d][k][j][i] with the face index fastest
+    // along d (the x block (nx+1) ny nz bytes, then y, then z)
+    constexpr bool REC_FLAGS = POS == 2;
 
     Real* Wp = reinterpret_cast<Real*>(smem_raw);
     Real* FB = Wp + TL::WP_SIZE;
@@ -182,7 +189,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     Real* DZY = DZX + 2 * TL::RX;   // [2][BY+4][BX]   (v, w) d/dz, y-face region
     Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
     Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NCELL]  x/y partial sums of R
-    Real* AZ = ACC + TL::ACC_SIZE;  // [BY+2][BX+2]    THINC: d(alpha)/dz, tile and 1-cell ring
+    Real* AZ = ACC + TL::ACC_SIZE;  // [BY+2][BX+2]    THINC: d(psi)/dz, tile and 1-cell ring
 
     const Material<Real> mat = a.mat;
     const Tolerances<Real> tol = a.tol;
@@ -217,10 +224,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V, interior_xy);
         cons_to_prim<Real, MODEL>(mat, u, w);
     };
-    auto stage_w = [&](int i, int j, const Real* w) {
+    auto stage_w = [&](int i, int j, const Real* w, Real psi) {
 #pragma unroll
         for (int f = 0; f < NC; f++) wp(f, i, j) = w[f];
         if constexpr (VISC) wp(NC, i, j) = w[P] * rcp(w[0]);  // T = p / rho
+        if constexpr (THINC) wp(NC, i, j) = psi;
     };
 
     // reconstruction variant: WENO5-Z of primitive variables per cell (both faces of a
@@ -232,6 +240,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     // register window W(s-3 .. s+2) of the own column
     constexpr int NWIN = FACE ? 7 : 6, WO = FACE ? 1 : 0;  // face tasks need s-4 .. s+2
     Real win[NWIN][NC];
+    // THINC: psi of the window's volume fractions (thinc_psi), computed once per plane
+    Real psw[THINC ? NWIN : 1];
     // viscous: two warm-up planes for the in-plane derivatives of the first z faces;
     // THINC: one, for the in-plane volume-fraction gradient of cell z0-1
     const int s_begin = VISC ? z0 - 2 : (THINC ? z0 - 1 : z0);
@@ -241,6 +251,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         else
 #pragma unroll
             for (int f = 0; f < NC; f++) win[q][f] = Real(1);
+        if constexpr (THINC) psw[q] = thinc_psi(win[q][6]);
     }
 
     Real vminus[NC];          // v^-_{s-3/2} from the reconstruction of cell s-2
@@ -249,7 +260,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     Real Fzl[NC];             // flux at the lower z face of cell s-2 (face s-5/2)
     Real uhzl = 0;            // its upwinded normal velocity (DIM)
     Real Dc[3][4];            // NS: (dw/dx, du/dx, dw/dy, dv/dy) at planes s-3, s-2, s-1
-    Real Ag[2][2] = {{0, 0}, {0, 0}};  // THINC: (d alpha/dx, d alpha/dy) of the own column at planes s-2, s-1
+    Real Ag[2][2] = {{0, 0}, {0, 0}};  // THINC: (d psi/dx, d psi/dy) of the own column at planes s-2, s-1
 #pragma unroll
     for (int m = 0; m < NC; m++) {
         vminus[m] = 0;
@@ -285,6 +296,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             if constexpr (LATE_OWN) load_own();
             apply_reflections(raw, V, rrefl);
             cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
+            if constexpr (THINC) psw[NWIN - 1] = thinc_psi(win[NWIN - 1][6]);
         };
         if constexpr (!LATE_OWN) load_own();
         const bool xy = (s >= z0) && (s < z1);
@@ -380,7 +392,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // the plane buffer is overwritten below: after a step with x/y phases their
             // barriers already ordered every read of it; after a warm-up step (only the
             // in-plane derivatives read it) a barrier is needed here
-            // THINC: alpha of the 1-cell ring at planes s-1 and s+1 for d(alpha)/dz at
+            // THINC: alpha of the 1-cell ring at planes s-1 and s+1 for d(psi)/dz at
             // plane s (highest-numbered threads), issued with the step's other loads
             Real ring_am = 0, ring_ap = 0;
             int ring_i = 0, ring_j = 0;
@@ -413,19 +425,22 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
             if (!prev_xy) __syncthreads();
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
-            if (has_cell) stage_w(tx, ty, win[3 + WO]);
+            if (has_cell) stage_w(tx, ty, win[3 + WO], psw[THINC ? 3 + WO : 0]);
             if constexpr (THINC) {
-                // d(alpha)/dz at plane s (second-order central): own column from the
+                // d(psi)/dz at plane s (second-order central): own column from the
                 // window, the 1-cell ring from memory (highest-numbered threads)
                 const Real hz = Real(0.5) * idz;
-                if (has_cell) AZ[(ty + 1) * (BX + 2) + tx + 1] = (win[4 + WO][6] - win[2 + WO][6]) * hz;
-                if (NT - 1 - tid < TL::NRING) AZ[(ring_j + 1) * (BX + 2) + ring_i + 1] = (ring_ap - ring_am) * hz;
+                if (has_cell) AZ[(ty + 1) * (BX + 2) + tx + 1] = (psw[4 + WO] - psw[2 + WO]) * hz;
+                if (NT - 1 - tid < TL::NRING)
+                    AZ[(ring_j + 1) * (BX + 2) + ring_i + 1] = (thinc_psi(ring_ap) - thinc_psi(ring_am)) * hz;
             }
             if (has_halo) {
                 Real w[NC];
                 apply_reflections(hu, V, hrefl);
                 cons_to_prim<Real, MODEL>(mat, hu, w);
-                stage_w(hi, hj, w);
+                Real hpsi = 0;
+                if constexpr (THINC) hpsi = thinc_psi(w[6]);
+                stage_w(hi, hj, w, hpsi);
             }
             if constexpr (VISC) {
                 if (xy) {
@@ -472,9 +487,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Dnew[3] = dcell(wp(V + 1, tx, ty - 2), wp(V + 1, tx, ty - 1), wp(V + 1, tx, ty + 1), wp(V + 1, tx, ty + 2), i12y);
             }
             if (THINC && has_cell) {
-                // in-plane volume-fraction gradient of the own column (THINC at the z faces)
-                Anew[0] = (wp(6, tx + 1, ty) - wp(6, tx - 1, ty)) * (Real(0.5) * idx);
-                Anew[1] = (wp(6, tx, ty + 1) - wp(6, tx, ty - 1)) * (Real(0.5) * idy);
+                // in-plane gradient of psi of the own column (THINC at the z faces)
+                Anew[0] = (wp(NC, tx + 1, ty) - wp(NC, tx - 1, ty)) * (Real(0.5) * idx);
+                Anew[1] = (wp(NC, tx, ty + 1) - wp(NC, tx, ty - 1)) * (Real(0.5) * idy);
             }
         } else {
             convert_own();
@@ -537,23 +552,31 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     // interface cells s-2 (its +z face) and s-1 (its -z face)
                     const Real hz = Real(0.5) * idz;
                     const Real a0 = win[WO][6], a1 = win[1 + WO][6], a2 = win[2 + WO][6], a3 = win[3 + WO][6];
-                    Real af, gz = (a2 - a0) * hz;
+                    Real af, gz = (psw[2 + WO] - psw[WO]) * hz;
                     if (thinc_face(a0, a1, a2, gz, Ag[0][0] * Ag[0][0] + Ag[0][1] * Ag[0][1] + gz * gz, 1, af))
                         thinc_state(af, win[1 + WO][0], win[1 + WO][1], a1, wl);
-                    gz = (a3 - a1) * hz;
+                    gz = (psw[3 + WO] - psw[1 + WO]) * hz;
                     if (thinc_face(a1, a2, a3, gz, Ag[1][0] * Ag[1][0] + Ag[1][1] * Ag[1][1] + gz * gz, 0, af))
                         thinc_state(af, win[2 + WO][0], win[2 + WO][1], a2, wr);
                 }
                 if constexpr (POS) {
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+                    const bool il = inadmissible_w<Real, MODEL>(mat, tol, wl);
+                    if (il)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wl[m] = win[1 + WO][m];
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+                    const bool ir = inadmissible_w<Real, MODEL>(mat, tol, wr);
+                    if (ir)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wr[m] = win[2 + WO][m];
                     hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
-                    if (flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1 + WO], win[2 + WO], F, uh, lamz))
-                        hllc<Real, MODEL, 2>(mat, win[1 + WO], win[2 + WO], F, uh);
+                    const bool fl = flux_limiter_trips<Real, MODEL, 2>(mat, tol, win[1 + WO], win[2 + WO], F, uh, lamz);
+                    if (fl) hllc<Real, MODEL, 2>(mat, win[1 + WO], win[2 + WO], F, uh);
+                    if constexpr (REC_FLAGS) {
+                        // z face s-1 (between cells s-2 and s-1)
+                        if (own_valid)
+                            a.flags[a.flag_off[2] + ((long long)(s - 1) * a.ny + gy) * a.nx + gx] =
+                                (unsigned char)((il ? 1 : 0) | (ir ? 2 : 0) | (fl ? 4 : 0));
+                    }
                 } else {
                     hllc<Real, MODEL, 2>(mat, wl, wr, F, uh);
                 }
@@ -675,12 +698,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     // interface cells f-1 (its +x face) and f (its -x face)
                     const Real hx = Real(0.5) * idx, hy = Real(0.5) * idy;
                     const Real am = wp(6, f - 2, j), a0 = wp(6, f - 1, j), a1 = wp(6, f, j), ap = wp(6, f + 1, j);
-                    Real af, gx = (a1 - am) * hx;
-                    Real gy = (wp(6, f - 1, j + 1) - wp(6, f - 1, j - 1)) * hy, gz = AZ[(j + 1) * (BX + 2) + f];
+                    Real af, gx = (wp(NC, f, j) - wp(NC, f - 2, j)) * hx;
+                    Real gy = (wp(NC, f - 1, j + 1) - wp(NC, f - 1, j - 1)) * hy, gz = AZ[(j + 1) * (BX + 2) + f];
                     if (thinc_face(am, a0, a1, gx, gx * gx + gy * gy + gz * gz, 1, af))
                         thinc_state(af, wp(0, f - 1, j), wp(1, f - 1, j), a0, wl);
-                    gx = (ap - a0) * hx;
-                    gy = (wp(6, f, j + 1) - wp(6, f, j - 1)) * hy;
+                    gx = (wp(NC, f + 1, j) - wp(NC, f - 1, j)) * hx;
+                    gy = (wp(NC, f, j + 1) - wp(NC, f, j - 1)) * hy;
                     gz = AZ[(j + 1) * (BX + 2) + f + 1];
                     if (thinc_face(a0, a1, ap, gx, gx * gx + gy * gy + gz * gz, 0, af))
                         thinc_state(af, wp(0, f, j), wp(1, f, j), a1, wr);
@@ -692,15 +715,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         wi[m] = wp(m, f - 1, j);
                         wj[m] = wp(m, f, j);
                     }
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+                    const bool il = inadmissible_w<Real, MODEL>(mat, tol, wl);
+                    if (il)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wl[m] = wi[m];
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+                    const bool ir = inadmissible_w<Real, MODEL>(mat, tol, wr);
+                    if (ir)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wr[m] = wj[m];
                     hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
-                    if (flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx))
-                        hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
+                    const bool fl = flux_limiter_trips<Real, MODEL, 0>(mat, tol, wi, wj, F, uh, lamx);
+                    if (fl) hllc<Real, MODEL, 0>(mat, wi, wj, F, uh);
+                    if constexpr (REC_FLAGS) {
+                        // x face x0+f (between cells x0+f-1 and x0+f) of row y0+j, plane s
+                        if (x0 + f <= a.nx && y0 + j < a.ny)
+                            a.flags[a.flag_off[0] + ((long long)s * a.ny + y0 + j) * (a.nx + 1) + x0 + f] =
+                                (unsigned char)((il ? 1 : 0) | (ir ? 2 : 0) | (fl ? 4 : 0));
+                    }
                 } else {
                     hllc<Real, MODEL, 0>(mat, wl, wr, F, uh);
                 }
@@ -799,12 +830,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     // interface cells of rows f-1 (its +y face) and f (its -y face)
                     const Real hx = Real(0.5) * idx, hy = Real(0.5) * idy;
                     const Real am = wp(6, i, f - 2), a0 = wp(6, i, f - 1), a1 = wp(6, i, f), ap = wp(6, i, f + 1);
-                    Real af, gy = (a1 - am) * hy;
-                    Real gx = (wp(6, i + 1, f - 1) - wp(6, i - 1, f - 1)) * hx, gz = AZ[f * (BX + 2) + i + 1];
+                    Real af, gy = (wp(NC, i, f) - wp(NC, i, f - 2)) * hy;
+                    Real gx = (wp(NC, i + 1, f - 1) - wp(NC, i - 1, f - 1)) * hx, gz = AZ[f * (BX + 2) + i + 1];
                     if (thinc_face(am, a0, a1, gy, gx * gx + gy * gy + gz * gz, 1, af))
                         thinc_state(af, wp(0, i, f - 1), wp(1, i, f - 1), a0, wl);
-                    gy = (ap - a0) * hy;
-                    gx = (wp(6, i + 1, f) - wp(6, i - 1, f)) * hx;
+                    gy = (wp(NC, i, f + 1) - wp(NC, i, f - 1)) * hy;
+                    gx = (wp(NC, i + 1, f) - wp(NC, i - 1, f)) * hx;
                     gz = AZ[(f + 1) * (BX + 2) + i + 1];
                     if (thinc_face(a0, a1, ap, gy, gx * gx + gy * gy + gz * gz, 0, af))
                         thinc_state(af, wp(0, i, f), wp(1, i, f), a1, wr);
@@ -816,15 +847,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                         wi[m] = wp(m, i, f - 1);
                         wj[m] = wp(m, i, f);
                     }
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wl))
+                    const bool il = inadmissible_w<Real, MODEL>(mat, tol, wl);
+                    if (il)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wl[m] = wi[m];
-                    if (inadmissible_w<Real, MODEL>(mat, tol, wr))
+                    const bool ir = inadmissible_w<Real, MODEL>(mat, tol, wr);
+                    if (ir)
 #pragma unroll
                         for (int m = 0; m < NC; m++) wr[m] = wj[m];
                     hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
-                    if (flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy))
-                        hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
+                    const bool fl = flux_limiter_trips<Real, MODEL, 1>(mat, tol, wi, wj, F, uh, lamy);
+                    if (fl) hllc<Real, MODEL, 1>(mat, wi, wj, F, uh);
+                    if constexpr (REC_FLAGS) {
+                        // y face y0+f (between rows y0+f-1 and y0+f) of column x0+i, plane s
+                        if (y0 + f <= a.ny && x0 + i < a.nx)
+                            a.flags[a.flag_off[1] + ((long long)s * (a.ny + 1) + y0 + f) * a.nx + x0 + i] =
+                                (unsigned char)((il ? 1 : 0) | (ir ? 2 : 0) | (fl ? 4 : 0));
+                    }
                 } else {
                     hllc<Real, MODEL, 1>(mat, wl, wr, F, uh);
                 }
@@ -899,6 +938,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         for (int q = 0; q < NWIN - 1; q++)
 #pragma unroll
             for (int f = 0; f < NC; f++) win[q][f] = win[q + 1][f];
+        if constexpr (THINC) {
+#pragma unroll
+            for (int q = 0; q < NWIN - 1; q++) psw[q] = psw[q + 1];
+        }
     }
     if (a.inv_max) {
         // block maximum of the inverse time step, one atomic per workgroup
@@ -924,7 +967,7 @@ constexpr int stage_waves()
     return sizeof(Real) == 4 ? WAVES_PER_EU_F32 : WAVES_PER_EU;
 }
 
-template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
+template <typename Real, int MODEL, int POS, int REC, int VMODE, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const StageArgs<Real> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -937,7 +980,7 @@ __global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const S
 // Many independent problems in one launch: the workgroups of problem r are
 // first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
 // and limiter setting for every problem of the launch).
-template <typename Real, int MODEL, bool POS, int BX, int BY, int NTH>
+template <typename Real, int MODEL, int POS, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, stage_waves<Real>())
     batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first, const int n)
 {
@@ -954,7 +997,7 @@ __global__ void __launch_bounds__(NTH, stage_waves<Real>())
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Real, int MODEL, bool POS, int REC, int VMODE, int BX, int BY, int NTH>
+template <typename Real, int MODEL, int POS, int REC, int VMODE, int BX, int BY, int NTH>
 static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
     using TL = Tile<Real, MODEL, BX, BY, NTH, MODEL == NS && VMODE != VM_EXT && VMODE != VM_EXT_LAW,
@@ -975,8 +1018,11 @@ static hipError_t launch_tile(const StageArgs<Real>& args, const LaunchGeom& g, 
 template <typename Real, int MODEL, int REC, int VMODE>
 static hipError_t launch_pos(const StageArgs<Real>& args, const LaunchGeom& g, hipStream_t st)
 {
-    if (args.positivity) return launch_tile<Real, MODEL, true, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
-    return launch_tile<Real, MODEL, false, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    if (args.positivity) {
+        if (args.flags) return launch_tile<Real, MODEL, 2, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+        return launch_tile<Real, MODEL, 1, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
+    }
+    return launch_tile<Real, MODEL, 0, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>(args, g, st);
 }
 
 // every variant of one precision, model and reconstruction (explicitly instantiated
@@ -1017,7 +1063,7 @@ hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStr
     }
 }
 
-template <typename Real, int MODEL, bool POS>
+template <typename Real, int MODEL, int POS>
 static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, int n, int nblocks, hipStream_t st)
 {
     using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>;
@@ -1040,14 +1086,14 @@ hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, 
 {
     switch (model) {
     case EULER:
-        return pos ? launch_batch_tile<Real, EULER, true>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, EULER, false>(args, first, n, nblocks, st);
+        return pos ? launch_batch_tile<Real, EULER, 1>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, EULER, 0>(args, first, n, nblocks, st);
     case NS:
-        return pos ? launch_batch_tile<Real, NS, true>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, NS, false>(args, first, n, nblocks, st);
+        return pos ? launch_batch_tile<Real, NS, 1>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, NS, 0>(args, first, n, nblocks, st);
     default:
-        return pos ? launch_batch_tile<Real, DIM, true>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, DIM, false>(args, first, n, nblocks, st);
+        return pos ? launch_batch_tile<Real, DIM, 1>(args, first, n, nblocks, st)
+                   : launch_batch_tile<Real, DIM, 0>(args, first, n, nblocks, st);
     }
 }
 

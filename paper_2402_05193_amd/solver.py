@@ -16,7 +16,7 @@ import torch
 EULER, NS, DIM = 0, 1, 2
 F64, F32 = 0, 1
 PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
-CASE_UNIFORM, CASE_TGV, CASE_RIEMANN, CASE_SBI = 0, 1, 2, 3
+CASE_UNIFORM, CASE_TGV, CASE_RIEMANN, CASE_SBI, CASE_GAUSS_WAVE, CASE_ISENTROPIC_VORTEX = 0, 1, 2, 3, 4, 5
 ABI_VERSION = 3
 
 OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
@@ -24,7 +24,8 @@ OK, EINVAL, ENULL, EALIGN, EUNSUPPORTED, EHIP, EINADMISSIBLE, ENONFINITE = 0, -1
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
-EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rhs_ws", "rk3_stage",
+EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rhs_ws",
+            "limiter_flag_bytes", "rhs_flags", "rk3_stage",
             "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "adjoint_workspace_bytes",
             "rk3_step_adjoint", "check_state", "workspace_time",
             "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
@@ -150,6 +151,8 @@ def lib():
         L.cons_to_prim.argtypes = [cp, vp, vp, vp]
         L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
         L.rhs_ws.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
+        L.limiter_flag_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+        L.rhs_flags.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp, vp]
         L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
         L.rk3_stage3_cfl.argtypes = [cp, vp, vp, vp, vp, vp, vp, vp]
         L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
@@ -264,6 +267,38 @@ def rhs(cfg: Config, U: torch.Tensor, R: torch.Tensor, dt: float = 0.0, stream=N
     else:
         _check(lib().rhs_ws(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _ptr(ws), _stream(stream)))
     return R
+
+
+def limiter_flag_bytes(cfg: Config) -> int:
+    c = cfg.c_struct()
+    out = ctypes.c_size_t(0)
+    _check(lib().limiter_flag_bytes(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+def rhs_flags(cfg: Config, U: torch.Tensor, R: torch.Tensor, dt: float = 0.0, flags: torch.Tensor | None = None,
+              ws=None, stream=None):
+    """R = R_NSE(U) and the limiter decisions of every face (uint8 tensor of
+    limiter_flag_bytes(cfg) bytes: x faces [nz][ny][nx+1], then y [nz][ny+1][nx], then
+    z [nz+1][ny][nx]; bit 0/1: interpolation limiter on the left/right state, bit 2:
+    flux limiter).  Returns (R, [flags_x, flags_y, flags_z]) as views."""
+    _state(cfg, U, "U")
+    _state(cfg, R, "R")
+    nb = limiter_flag_bytes(cfg)
+    if flags is None:
+        flags = torch.empty(nb, dtype=torch.uint8, device=U.device)
+    if flags.dtype != torch.uint8 or not flags.is_contiguous() or flags.numel() != nb or not flags.is_cuda:
+        raise ValueError(f"flags: expected a contiguous device uint8 tensor of {nb} bytes")
+    if ws is None and cfg.visc_order == 6:
+        ws = workspace(cfg)
+    c = cfg.c_struct()
+    _check(lib().rhs_flags(ctypes.byref(c), _ptr(U), _ptr(R), float(dt), _ptr(flags), _ptr(ws), _stream(stream)))
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    n0 = (nx + 1) * ny * nz
+    n1 = nx * (ny + 1) * nz
+    views = [flags[:n0].view(nz, ny, nx + 1), flags[n0:n0 + n1].view(nz, ny + 1, nx),
+             flags[n0 + n1:].view(nz + 1, ny, nx)]
+    return R, views
 
 
 def rk3_stage(cfg: Config, stage: int, Un, Uk, Uout, dt: float = 0.0, dt_dev: torch.Tensor | None = None,

@@ -138,6 +138,24 @@ def test_init_state_tgv_matches_generator():
     assert np.all(comp_rel(host(Ud), Uo) <= 1e-14)
 
 
+def test_init_state_convergence_cases():
+    """The convergence test's Gaussian density wave (exact cell averages, along each
+    axis) and the isentropic vortex (5 x 5 Gauss cell averages) against the host
+    generators."""
+    for axis in range(3):
+        case = WL.gauss_wave(64, axis=axis)
+        sc = solver_cfg(case)
+        Ud = S.init_state(sc, S.CASE_GAUSS_WAVE, [axis, 1.0, 1.0], S.empty_state(sc))
+        Uo = O.prim_to_cons(oracle_cfg(case), case.W)
+        assert np.all(comp_rel(host(Ud), Uo) <= 1e-14), axis
+    from test_oracle_accuracy import _vortex_cell_averages
+    n = 32
+    h = 10.0 / n
+    sc = S.Config(nx=n, ny=n, nz=1, dx=h, dy=h, dz=h)
+    Ud = S.init_state(sc, S.CASE_ISENTROPIC_VORTEX, [5.0, 5.0, 5.0, 1.0, 1.0], S.empty_state(sc))
+    assert np.all(comp_rel(host(Ud), _vortex_cell_averages(n, 0.0)) <= 1e-14)
+
+
 def test_init_state_sbi_matches_generator():
     case = WL.shock_bubble(32, 16, 16)
     sc = solver_cfg(case)
@@ -259,6 +277,24 @@ def test_hundred_steps_c1():
     assert t == pytest.approx(t_o, rel=1e-15)
     err = comp_rel(host(Ud), Uo)
     print(f"[parity] 100 steps rel err {err}", flush=True)
+    assert np.all(err <= STEP_TOL), err
+
+
+def test_hundred_steps_ns_tgv64():
+    """The viscous benchmark case at 64^3: 100 CFL-0.5 steps of the GPU against the
+    oracle (spec bar 1e-10 per component after 100 steps) and the simulated time."""
+    case = WL.taylor_green(64, viscous=True)
+    oc = oracle_cfg(case)
+    U = O.prim_to_cons(oc, case.W)
+    print("[parity] 100 CFL steps NS TGV 64^3 oracle ...", flush=True)
+    Uo, t_o = O.advance(oc, U, 100, dt=0.0, cfl=0.5)
+    sc = solver_cfg(case, cfl=0.5)
+    Ud = dev(U)
+    t = S.advance(sc, Ud, 100, 0.0, S.workspace(sc), t=0.0)
+    err = comp_rel(host(Ud), Uo)
+    print(f"[parity] NS TGV 64^3 100 steps rel err {np.array2string(err, precision=2)}, time {t:.12e} "
+          f"vs {t_o:.12e}", flush=True)
+    assert t == pytest.approx(t_o, rel=1e-13)
     assert np.all(err <= STEP_TOL), err
 
 
