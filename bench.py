@@ -68,7 +68,7 @@ PROFILE_MD = os.path.join(ROOT, "profiles", "stage_kernel_ns_tgv256_f64.md")
 
 # the benchmarked instantiation: stage_kernel<double, NS, positivity off, primitive
 # reconstruction, constant viscosity, 16x16 tile, 256 threads>
-STAGE_KERNEL_SYMBOL = "_ZN2fv12stage_kernelIdLi1ELb0ELi0ELi0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE"
+STAGE_KERNEL_SYMBOL = "_ZN2fv12stage_kernelIdLi1ELi0ELi0ELi0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE"
 
 
 def _elf_sections(elf: bytes):

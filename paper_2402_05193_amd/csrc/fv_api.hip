@@ -444,7 +444,7 @@ int rhs_flags(const fv_config* cfg, const void* U, void* R, double dt, uint8_t* 
         // no limiter acts: every decision byte is 0
         long long off[3], total;
         flag_offsets(cfg, off, &total);
-        hipError_t e = hipMemsetAsync(flags, 0, (size_t)total, st);
+        hipError_t e = fv::launch_fill_u8(flags, total, 0, st);
         if (e != hipSuccess) return hip_fail(e, "rhs_flags: clear");
         return stage_dispatch(cfg, 0, U, U, R, dt, nullptr, st, nullptr, wp);
     }

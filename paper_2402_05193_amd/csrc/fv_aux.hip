@@ -296,6 +296,21 @@ hipError_t launch_batch_dt_finish(const BatchScalars* s, int n, hipStream_t st)
     return hipGetLastError();
 }
 
+__global__ void fill_u8_kernel(unsigned char* __restrict__ p, long long n, unsigned char v)
+{
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+hipError_t launch_fill_u8(unsigned char* p, long long n, unsigned char v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st)
 {
     hipLaunchKernelGGL(reset_u64_kernel, dim3(1), dim3(64), 0, st, inv_max);

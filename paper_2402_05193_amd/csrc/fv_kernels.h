@@ -155,6 +155,8 @@ hipError_t launch_check(const AuxArgs& a, const Real* U, long long* ws_words, hi
 hipError_t launch_add_scalar(double* t_acc, const double* dt, hipStream_t st);
 // *inv_max = 0
 hipError_t launch_reset_max(unsigned long long* inv_max, hipStream_t st);
+// p[0 .. n) = v (a kernel, so that it can be captured in a graph)
+hipError_t launch_fill_u8(unsigned char* p, long long n, unsigned char v, hipStream_t st);
 // t_acc (optional) += *dt_prev;  *dt_out = cfl / max;  *inv_max = 0
 hipError_t launch_dt_finish(unsigned long long* inv_max, double cfl, double* dt_out, double* t_acc,
                             const double* dt_prev, hipStream_t st);
