@@ -224,6 +224,24 @@ int compute_dt(const fv_config* cfg, const void* U, double* dt_dev, void* ws, vo
 int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws,
             void* stream);
 
+/* Size of the fixed device array that advance_noalloc uses as its workspace
+ * (one per device, held until the process ends): 64 MiB, e.g. a 64^3 FP64
+ * single-phase (42 MB) or five-equation problem (59 MB). */
+#define FV_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* advance without any device allocation, for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same TVD-RK3 steps as advance(cfg, U, nsteps, dt, NULL,
+ * ws, stream), bit for bit, with ws taken from the library's fixed array of
+ * FV_NOALLOC_SCRATCH_BYTES bytes on the current device instead of the caller's
+ * workspace.  Problems whose workspace_bytes(cfg) exceed it are rejected with
+ * FV_EINVAL.  No simulated-time read-back (t_inout of advance).  Every call on a
+ * device shares that device's array: calls that overlap in time on one device
+ * (different streams or host threads) race and must not be issued; calls in one
+ * stream order are safe.  The first call on a device looks up the array's
+ * address there (once per device). */
+int advance_noalloc(const fv_config* cfg, void* U, int32_t nsteps, double dt, void* stream);
+
 /* Discrete adjoint (the reverse-mode derivative the paper takes by automatic
  * differentiation of the solver, Sec. 6): the vector-Jacobian product
  *   Ubar = (dR/dU)^T Rbar

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/fvrk3.h"
@@ -521,16 +522,12 @@ int compute_dt(const fv_config* cfg, const void* U, double* dt_dev, void* ws, vo
     return FV_OK;
 }
 
-int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws, void* stream)
+// advance with a validated configuration and workspace (advance, advance_noalloc)
+static int advance_impl(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws,
+                        hipStream_t st)
 {
-    int r = validate(cfg);
-    if (r) return r;
-    if ((r = check_ptr(U, "U")) || (r = check_ptr(ws, "ws"))) return r;
-    if (nsteps < 0) return fail(FV_EINVAL, "nsteps must be >= 0");
+    int r;
     const bool cfl_mode = !(dt > 0);
-    if (cfl_mode && !(cfg->cfl > 0)) return fail(FV_EINVAL, "cfl must be > 0 when dt <= 0");
-    if (!cfl_mode && !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite");
-    hipStream_t st = (hipStream_t)stream;
     const WsLayout w = ws_layout(cfg, ws);
     const fv::AuxArgs a = aux_args(cfg);
     const double mu = cfg->model == FV_NS ? cfg->mu : 0.0;
@@ -565,6 +562,74 @@ int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_
         }
     }
     return FV_OK;
+}
+
+int advance(const fv_config* cfg, void* U, int32_t nsteps, double dt, double* t_inout, void* ws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(U, "U")) || (r = check_ptr(ws, "ws"))) return r;
+    if (nsteps < 0) return fail(FV_EINVAL, "nsteps must be >= 0");
+    const bool cfl_mode = !(dt > 0);
+    if (cfl_mode && !(cfg->cfl > 0)) return fail(FV_EINVAL, "cfl must be > 0 when dt <= 0");
+    if (!cfl_mode && !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite");
+    return advance_impl(cfg, U, nsteps, dt, t_inout, ws, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// The workspace of advance_noalloc: one fixed array per device, resident while the
+// process lives.  Host code uses its device address from hipGetSymbolAddress (the
+// array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[FV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of the current device's scratch array, looked up once per device
+int scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "advance_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(FV_EUNSUPPORTED, "device index %d beyond %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "advance_noalloc: hipGetSymbolAddress");
+        if (!ptr || (uintptr_t)ptr % 256) return fail(FV_EHIP, "advance_noalloc: scratch address not usable");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int advance_noalloc(const fv_config* cfg, void* U, int32_t nsteps, double dt, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = check_ptr(U, "U"))) return r;
+    if (nsteps < 0) return fail(FV_EINVAL, "nsteps must be >= 0");
+    const bool cfl_mode = !(dt > 0);
+    if (cfl_mode && !(cfg->cfl > 0)) return fail(FV_EINVAL, "cfl must be > 0 when dt <= 0");
+    if (!cfl_mode && !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite");
+    size_t need = 0;
+    if ((r = workspace_bytes(cfg, &need))) return r;
+    if (need > (size_t)FV_NOALLOC_SCRATCH_BYTES)
+        return fail(FV_EINVAL, "advance_noalloc: the problem needs %zu bytes of workspace, more than the %zu of the "
+                               "fixed scratch array (use advance with a caller workspace)",
+                    need, (size_t)FV_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((r = scratch_of_current_device(&ws))) return r;
+    return advance_impl(cfg, U, nsteps, dt, nullptr, ws, (hipStream_t)stream);
 }
 
 static int adjoint_supported(const fv_config* cfg)

@@ -26,7 +26,7 @@ LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 
 EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rhs_ws",
             "limiter_flag_bytes", "rhs_flags", "rk3_stage",
-            "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "rhs_adjoint", "adjoint_workspace_bytes",
+            "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "advance_noalloc", "rhs_adjoint", "adjoint_workspace_bytes",
             "rk3_step_adjoint", "check_state", "workspace_time",
             "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
             "last_error"]
@@ -158,6 +158,7 @@ def lib():
         L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
         L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
         L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
+        L.advance_noalloc.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, vp]
         L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
         L.adjoint_workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
         L.rk3_step_adjoint.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
@@ -348,6 +349,19 @@ def advance(cfg: Config, U: torch.Tensor, nsteps: int, dt: float, ws: torch.Tens
         tp = ctypes.byref(tv)
     _check(lib().advance(ctypes.byref(c), _ptr(U), int(nsteps), float(dt), tp, _ptr(ws), _stream(stream)))
     return tv.value if tv is not None else None
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # FV_NOALLOC_SCRATCH_BYTES of include/fvrk3.h
+
+
+def advance_noalloc(cfg: Config, U: torch.Tensor, nsteps: int, dt: float, stream=None):
+    """advance without a caller workspace and without any device allocation (the
+    library's fixed per-device scratch array; problems whose workspace exceeds
+    NOALLOC_SCRATCH_BYTES are rejected)."""
+    _state(cfg, U, "U")
+    c = cfg.c_struct()
+    _check(lib().advance_noalloc(ctypes.byref(c), _ptr(U), int(nsteps), float(dt), _stream(stream)))
+    return U
 
 
 def rhs_adjoint(cfg: Config, U, Rbar, Ubar, ws=None, stream=None):

@@ -117,3 +117,18 @@ def test_workspace_and_ncomp():
     cs = c.c_struct()
     assert S.lib().adjoint_workspace_bytes(ctypes.byref(cs), ctypes.byref(out)) == S.OK
     assert out.value == 5 * pad
+
+
+def test_advance_noalloc_rejects_problems_beyond_its_scratch():
+    """advance_noalloc checks the workspace size before any device work."""
+    c = cfg(nx=256, ny=256, nz=256, model=S.NS, mu=1e-3)
+    cs = c.c_struct()
+    assert S.workspace_bytes(c) > S.NOALLOC_SCRATCH_BYTES
+    assert S.lib().advance_noalloc(ctypes.byref(cs), 256, 1, 1e-3, None) == S.EINVAL
+    assert "scratch" in S.last_error()
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define FV_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == S.NOALLOC_SCRATCH_BYTES
