@@ -31,8 +31,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector
-PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector
+# MI355X FP32 vector: 157.3 TFLOP/s is the packed (two-wide) rate; the library is built
+# without packed FP32 operations, so its FP32 kernels issue at the FP64 vector rate
+PEAK_FP32_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
+PEAK_VALU_LANE_INSTS = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic floating-point operations per cell per stage (+ - * / sqrt min
 # max abs and comparisons each count 1), from the formulas of the scheme:
@@ -124,20 +128,35 @@ def stage_kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str):
-    """HBM bytes per stage-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
-    kernel of known size) recorded in the committed rocprofv3 summary, if it was
-    taken on the current kernel (same fingerprint) and workload; else None."""
+def _profile_record(kind: str, workload_key: str):
+    """The numbers of a record line ('<kind>-record: kernel=<fingerprint> workload=<key>
+    name=value ...') of the committed rocprofv3 summary, if it was taken on the current
+    kernel (same fingerprint) and workload; else None."""
     if not os.path.exists(PROFILE_MD):
         return None
     want = stage_kernel_hash()
-    pat = re.compile(r"traffic-record: kernel=(\w+) workload=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)")
+    pat = re.compile(kind + r"-record: kernel=(\w+) workload=(\S+)((?: \w+=[\d.e+-]+)+)")
     with open(PROFILE_MD) as fh:
         for line in fh:
             m = pat.search(line)
             if m and m.group(1) == want and m.group(2) == workload_key:
-                return int(m.group(3)) + int(m.group(4))
+                return {k: float(v) for k, v in re.findall(r"(\w+)=([\d.e+-]+)", m.group(3))}
     return None
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per stage-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel of known size) recorded in the committed rocprofv3 summary for the current
+    kernel and workload; else None."""
+    r = _profile_record("traffic", workload_key)
+    return int(r["fetch_bytes"] + r["write_bytes"]) if r else None
+
+
+def measured_valu_insts_per_cell(workload_key: str):
+    """VALU lane-instructions per cell and launch (SQ_INSTS_VALU x 64 / cells) recorded in
+    the committed rocprofv3 summary for the current kernel and workload; else None."""
+    r = _profile_record("valu", workload_key)
+    return r["insts_per_cell"] if r else None
 
 
 def bytes_per_cell(nc: int, es: int, stage: int) -> int:
@@ -145,46 +164,75 @@ def bytes_per_cell(nc: int, es: int, stage: int) -> int:
     return (2 if stage == 1 else 3) * nc * es
 
 
+def _native_oracle():
+    """The oracle's source built for this host (-O3 -march=native, contraction off, so
+    the same results as the reference build), into a temporary directory; None if the
+    host has no C compiler."""
+    import subprocess
+    import tempfile
+    import oracle as O
+    out = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle_native.so")
+    try:
+        subprocess.run(["make", "-s", "-C", os.path.join(ROOT, "oracle"), "-B", "native", f"NATIVE_OUT={out}"],
+                       check=True, capture_output=True)
+    except (OSError, subprocess.CalledProcessError):
+        return None
+    O._lib = O._load(out)
+    return out
+
+
 def run_oracle_baseline(n: int, model: int) -> dict:
-    """The FP64 oracle timed on this host on a bounded sample of the same workload:
-    one full TVD-RK3 step (three right-hand sides) of the benchmarked problem."""
+    """The FP64 oracle timed on this host's cores on bounded samples of the workload:
+    one full TVD-RK3 step (three right-hand sides) of the benchmarked problem, plus one
+    step of its smaller sizes (C1 32^3 Euler, 128^3, and the 256 x 128 x 128
+    five-equation shock-bubble), and a 64^3 step on one thread."""
     import oracle as O
     from paper_2402_05193_amd import workloads as WL
-    if model == 2:
-        case = WL.shock_bubble(256, 128, 128) if n >= 256 else WL.shock_bubble(2 * n, n // 2, n // 2)
-    else:
-        case = WL.taylor_green(n, viscous=(model == 1))
-    cfg = O.Config(**case.cfg_kwargs())
-    U = O.prim_to_cons(cfg, case.W)
-    dt = O.compute_dt(cfg, U, 0.5)
+    native = _native_oracle()
     threads = O.max_threads()
-    t0 = time.perf_counter()
-    O.rk3_step(cfg, U, dt)
-    el = time.perf_counter() - t0
-    cells = cfg.nx * cfg.ny * cfg.nz
-    # the same on one thread, on a 64^3 block of the workload's kind (a few seconds)
+
+    def one_step(case):
+        cfg = O.Config(**case.cfg_kwargs())
+        U = O.prim_to_cons(cfg, case.W)
+        dt = O.compute_dt(cfg, U, 0.5)
+        t0 = time.perf_counter()
+        O.rk3_step(cfg, U, dt)
+        return cfg.nx * cfg.ny * cfg.nz * 3 / (time.perf_counter() - t0), time.perf_counter() - t0
+
+    if model == 2:
+        main_case = WL.shock_bubble(256, 128, 128) if n >= 256 else WL.shock_bubble(2 * n, n // 2, n // 2)
+    else:
+        main_case = WL.taylor_green(n, viscous=(model == 1))
+    value, el = one_step(main_case)
+    samples = {}
+    for name, case in (("c1_euler_tgv32", WL.taylor_green(32)),
+                       ("ns_tgv128", WL.taylor_green(128, viscous=True)),
+                       ("dim_sbi256x128x128", WL.shock_bubble(256, 128, 128))):
+        if name.startswith("dim") and model == 2 and n >= 256:
+            continue
+        v, t = one_step(case)
+        samples[name] = {"value": v, "seconds": t}
+    # one thread, a 64^3 block of the workload's kind
     small = WL.taylor_green(64, viscous=(model == 1)) if model != 2 else WL.shock_bubble(64, 32, 32)
-    cs = O.Config(**small.cfg_kwargs())
-    Us = O.prim_to_cons(cs, small.W)
     O.set_threads(1)
     try:
-        t1 = time.perf_counter()
-        O.rk3_step(cs, Us, O.compute_dt(cs, Us, 0.5))
-        el1 = time.perf_counter() - t1
+        v1, el1 = one_step(small)
     finally:
         O.set_threads(threads)
-    cells1 = cs.nx * cs.ny * cs.nz
     model_name = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model_name = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": cells * 3 / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one TVD-RK3 step (3 stages) of the same workload, {cfg.nx}x{cfg.ny}x{cfg.nz} FP64, "
-                      f"{el:.1f} s on {threads} threads",
-            "single_thread": {"value": cells1 * 3 / el1, "sample": f"one TVD-RK3 step at {cs.nx}x{cs.ny}x{cs.nz}, "
-                                                                  f"{el1:.1f} s on 1 thread"},
+    return {"value": value, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one TVD-RK3 step (3 stages) of the same workload, {main_case.nx}x{main_case.ny}x{main_case.nz} "
+                      f"FP64, {el:.1f} s on {threads} threads",
+            "build": "-O3 -march=native -ffp-contract=off (built on this host)" if native
+                     else "-O3 -ffp-contract=off (no compiler on this host for a native build)",
+            "other_samples": samples,
+            "single_thread": {"value": v1, "sample": f"one TVD-RK3 step at {small.nx}x{small.ny}x{small.nz}, "
+                                                     f"{el1:.1f} s on 1 thread"},
             "cpu_model": model_name}
 
 
@@ -272,23 +320,34 @@ def run_adjoint_bench(n: int = 64, nsteps: int = 100, every: int = 10) -> dict:
     torch.cuda.synchronize()
     rhs_ms = e0.elapsed_time(e1) / reps
     # forward alone, then forward + backward of the whole trajectory
-    X = U.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.advance(cfg, X, nsteps, dt, ws)
-    torch.cuda.synchronize()
-    fwd_s = time.perf_counter() - t0
-    U0 = U.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L = AD.kinetic_energy(cfg, AD.advance_fixed_dt(cfg, U0, nsteps, dt, every=every))
-    (g,) = torch.autograd.grad(L, U0)
-    torch.cuda.synchronize()
-    grad_s = time.perf_counter() - t0
+    fwd = []
+    for r in range(4):
+        X = U.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.advance(cfg, X, nsteps, dt, ws)
+        torch.cuda.synchronize()
+        if r > 0:
+            fwd.append(time.perf_counter() - t0)
+    fwd_s = sorted(fwd)[1]
+    # forward + gradient: one untimed run (kernels loaded, workspaces allocated), then the
+    # median of three timed runs
+    runs = []
+    for r in range(4):
+        U0 = U.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = AD.kinetic_energy(cfg, AD.advance_fixed_dt(cfg, U0, nsteps, dt, every=every))
+        (g,) = torch.autograd.grad(L, U0)
+        torch.cuda.synchronize()
+        if r > 0:
+            runs.append(time.perf_counter() - t0)
+    grad_s = sorted(runs)[1]
     return {"workload": f"gradient of kinetic energy after {nsteps} fixed-dt TVD-RK3 steps, {n}^3 decaying "
                         f"turbulence (Euler, FP64, WENO-Z eps 1e-6), checkpoints every {every} steps",
             "rhs_adjoint_ms": adj_ms, "rhs_ms": rhs_ms, "adjoint_over_rhs": adj_ms / rhs_ms,
             "forward_s": fwd_s, "forward_plus_gradient_s": grad_s, "gradient_over_forward": grad_s / fwd_s,
+            "timing": "median of 3 runs after one untimed run",
             "loss": float(L), "grad_finite": bool(torch.isfinite(g).all().item())}
 
 
@@ -451,6 +510,10 @@ def main():
                     + ("-teno" if args.scheme else "") + ("-v6" if cfg.visc_order == 6 else "")
                     + ("-thinc" if args.thinc else ""))
     traffic = measured_traffic(workload_key)
+    valu_per_cell = measured_valu_insts_per_cell(workload_key)
+    t_stage = mean_stage_ms * 1e-3
+    t_alu = flops_launch / (peak * 1e12)
+    t_hbm = alg_bytes / (PEAK_HBM_GBS * 1e9)
     out = {
         "metric": "cell-updates/s + % HBM roofline (RK3 stage, 256^3); batched p50/p99 latency",
         "value": value,
@@ -460,7 +523,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": None,             # one GPU: no scaling statement
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic (seeded analytic initial condition generated on the device)",
@@ -471,7 +534,17 @@ def main():
                      "stage2": sum(stage_ms[1]) / args.steps, "stage3": sum(stage_ms[2]) / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak, "traffic": traffic,
-                     "kernel": "stage_kernel", "flops_per_cell": fpc, "kernel_fingerprint": stage_kernel_hash() if default_kernel else None},
+                     "kernel": "stage_kernel", "flops_per_cell": fpc,
+                     "kernel_fingerprint": stage_kernel_hash() if default_kernel else None,
+                     # max(t_HBM, t_ALU) / t over the algorithmic bytes and operations: the
+                     # fraction of the attainable roofline, and the resource that sets it
+                     "attainable_frac": max(t_alu, t_hbm) / t_stage,
+                     "binding": "alu" if t_alu >= t_hbm else "hbm",
+                     # VALU lane-instructions the kernel issues (committed counters of this
+                     # kernel and workload) over the issue rate: the fraction of VALU issue
+                     "valu_insts_per_cell": valu_per_cell,
+                     "valu_issue_frac": (valu_per_cell * ncell / PEAK_VALU_LANE_INSTS / t_stage)
+                                        if valu_per_cell else None},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_cell_mean": alg_bytes / ncell,
                          "measured_copy_gbs": copy_gbs, "frac_of_copy": hbm_gbs / copy_gbs,

@@ -12,6 +12,7 @@ five-equation model ``U = (a1 rho1, a2 rho2, rho u, rho v, rho w, E, a1)``,
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -24,12 +25,16 @@ PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_FMA_PATH = os.path.join(_HERE, "liboracle_fma.so")
 _lib = None
+_fma_lib = None
 
 
 def build() -> None:
-    """Compile liboracle.so with the oracle's own Makefile."""
+    """Compile liboracle.so with the oracle's own Makefile, and the same source with
+    multiply-add contraction (liboracle_fma.so, used only to calibrate round-off floors)."""
     subprocess.run(["make", "-s", "-C", _HERE, "-B", "liboracle.so"], check=True)
+    subprocess.run(["make", "-s", "-C", _HERE, "-B", "fma", f"FMA_OUT={_FMA_PATH}"], check=True)
 
 
 class _Cfg(ctypes.Structure):
@@ -118,36 +123,61 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        cp = ctypes.POINTER(_Cfg)
-        L.orc_ncomp.argtypes = [cp]
-        L.orc_prim_to_cons.argtypes = [cp, dp, dp]
-        L.orc_cons_to_prim.argtypes = [cp, dp, dp]
-        L.orc_weno5z.argtypes = [ctypes.c_double] * 6
-        L.orc_weno5z.restype = ctypes.c_double
-        L.orc_teno6a_parts.argtypes = [dp, ctypes.c_double, dp]
-        L.orc_teno6a_parts.restype = ctypes.c_double
-        L.orc_thinc_faces.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
-        L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
-        L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double,
-                                    ctypes.POINTER(ctypes.c_uint8)]
-        L.orc_hllc_speeds.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
-        L.orc_thinc_beta.argtypes = [dp, dp, ctypes.c_int]
-        L.orc_thinc_beta.restype = ctypes.c_double
-        L.orc_rk3_stage.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double]
-        L.orc_dt.argtypes = [cp, dp, ctypes.c_double]
-        L.orc_dt.restype = ctypes.c_double
-        L.orc_advance.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
-        L.orc_advance.restype = ctypes.c_double
-        L.orc_char_matrices.argtypes = [cp, ctypes.c_int, dp, dp, dp]
-        L.orc_face_count.argtypes = [cp, ctypes.c_int]
-        L.orc_face_count.restype = ctypes.c_long
-        L.orc_max_threads.restype = ctypes.c_int
-        L.orc_set_threads.argtypes = [ctypes.c_int]
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def contracted():
+    """Within the block every oracle call runs the same source built with multiply-add
+    contraction (liboracle_fma.so): a second, equally valid rounding of every
+    operation, whose difference from the reference build is the oracle's own
+    round-off floor (including intermediate roundings that a one-ulp move of the
+    input does not reach)."""
+    global _lib, _fma_lib
+    saved = lib()
+    if _fma_lib is None:
+        if not os.path.exists(_FMA_PATH):
+            subprocess.run(["make", "-s", "-C", _HERE, "-B", "fma", f"FMA_OUT={_FMA_PATH}"], check=True)
+        _fma_lib = _load(_FMA_PATH)
+    _lib = _fma_lib
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _load(path):
+    """Load one build of the oracle and declare its entry points."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    cp = ctypes.POINTER(_Cfg)
+    L.orc_ncomp.argtypes = [cp]
+    L.orc_prim_to_cons.argtypes = [cp, dp, dp]
+    L.orc_cons_to_prim.argtypes = [cp, dp, dp]
+    L.orc_weno5z.argtypes = [ctypes.c_double] * 6
+    L.orc_weno5z.restype = ctypes.c_double
+    L.orc_teno6a_parts.argtypes = [dp, ctypes.c_double, dp]
+    L.orc_teno6a_parts.restype = ctypes.c_double
+    L.orc_thinc_faces.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    L.orc_hllc.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
+    L.orc_rhs.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]
+    L.orc_rhs_cells.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_uint8)]
+    L.orc_hllc_speeds.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
+    L.orc_thinc_beta.argtypes = [dp, dp, ctypes.c_int]
+    L.orc_thinc_beta.restype = ctypes.c_double
+    L.orc_rk3_stage.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double]
+    L.orc_dt.argtypes = [cp, dp, ctypes.c_double]
+    L.orc_dt.restype = ctypes.c_double
+    L.orc_advance.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    L.orc_advance.restype = ctypes.c_double
+    L.orc_char_matrices.argtypes = [cp, ctypes.c_int, dp, dp, dp]
+    L.orc_face_count.argtypes = [cp, ctypes.c_int]
+    L.orc_face_count.restype = ctypes.c_long
+    L.orc_max_threads.restype = ctypes.c_int
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    return L
 
 
 def _dp(a: np.ndarray):

@@ -23,11 +23,38 @@ import torch
 from . import solver as S
 
 
+# Workspaces of the forward and reverse sweeps, kept per (workspace size, device) and
+# reused by later calls on problems of the same size (the tensors are only scratch:
+# every call overwrites them before reading).  Trajectories differentiated at the
+# same time on one device (several streams or threads) would share them: run them
+# one after another.
+_WS: dict = {}
+
+
+def _scratch(kind: str, nbytes: int, device) -> torch.Tensor:
+    key = (kind, int(nbytes), str(device))
+    t = _WS.get(key)
+    if t is None:
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        _WS[key] = t
+    return t
+
+
+def _segment_states(every: int, like: torch.Tensor) -> torch.Tensor:
+    """Buffer for the recomputed states of one checkpoint segment (reused)."""
+    key = ("segment", every, tuple(like.shape), like.dtype, str(like.device))
+    t = _WS.get(key)
+    if t is None:
+        t = torch.empty((every,) + tuple(like.shape), dtype=like.dtype, device=like.device)
+        _WS[key] = t
+    return t
+
+
 class _Advance(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, cfg, nsteps, dt, every):
         U = U0.detach().clone().contiguous()
-        ws = S.workspace(cfg, U.device)
+        ws = _scratch("ws", S.workspace_bytes(cfg), U.device)
         ckpts = []
         for n in range(nsteps):
             if n % every == 0:
@@ -42,16 +69,18 @@ class _Advance(torch.autograd.Function):
         cfg, nsteps, dt, every = ctx.cfg, ctx.nsteps, ctx.dt, ctx.every
         ckpts = ctx.saved_tensors
         G = Ubar.detach().clone().contiguous()
-        ws = S.workspace(cfg, G.device)
-        aws = S.adjoint_workspace(cfg, G.device)
+        ws = _scratch("ws", S.workspace_bytes(cfg), G.device)
+        aws = _scratch("aws", S.adjoint_workspace_bytes(cfg), G.device)
+        states = _segment_states(every, G)
         for seg in range(len(ckpts) - 1, -1, -1):
             first = seg * every
             count = min(every, nsteps - first)
-            states = [ckpts[seg]]
-            U = ckpts[seg].clone()
-            for _ in range(count - 1):
-                S.rk3_step(cfg, U, dt, ws)
-                states.append(U.clone())
+            # states of the segment: the checkpoint, then each step recomputed in place
+            # from the previous one
+            states[0].copy_(ckpts[seg])
+            for n in range(1, count):
+                states[n].copy_(states[n - 1])
+                S.rk3_step(cfg, states[n], dt, ws)
             for n in range(count - 1, -1, -1):
                 S.rk3_step_adjoint(cfg, states[n], G, dt, aws)
         return G, None, None, None, None

@@ -373,11 +373,15 @@ def rhs_adjoint(cfg: Config, U, Rbar, Ubar, ws=None, stream=None):
     return Ubar
 
 
-def adjoint_workspace(cfg: Config, device="cuda") -> torch.Tensor:
+def adjoint_workspace_bytes(cfg: Config) -> int:
     c = cfg.c_struct()
     out = ctypes.c_size_t(0)
     _check(lib().adjoint_workspace_bytes(ctypes.byref(c), ctypes.byref(out)))
-    return torch.empty(out.value, dtype=torch.uint8, device=device)
+    return out.value
+
+
+def adjoint_workspace(cfg: Config, device="cuda") -> torch.Tensor:
+    return torch.empty(adjoint_workspace_bytes(cfg), dtype=torch.uint8, device=device)
 
 
 def rk3_step_adjoint(cfg: Config, Un: torch.Tensor, Ubar: torch.Tensor, dt: float, aws: torch.Tensor, stream=None):

@@ -52,10 +52,14 @@ def comp_rel(gpu, ref):
 
 
 def roundoff_floor(oc, U, dt, cells=None, trials=2, seed=1):
-    """Relative change of the oracle's own R when every input value moves by one
-    unit in the last place (random sign): the conditioning floor of the case.
-    In low-Mach flow the pressure flux (~1/(gamma Ma^2)) cancels in the flux
-    difference, so this floor can exceed 1e-12."""
+    """The oracle's own round-off floor of the case, per component: the larger of
+    (1) the relative change of its R when every input value moves by one unit in
+    the last place (random sign; the conditioning of the problem: in low-Mach flow
+    the pressure flux ~1/(gamma Ma^2) cancels in the flux difference, so this can
+    exceed 1e-12), and (2) the difference between the oracle and the same source
+    built with multiply-add contraction (every intermediate rounded differently,
+    e.g. inside THINC's exp / atanh / tanh chain, which an input move does not
+    reach)."""
     rng = np.random.default_rng(seed)
     R = O.rhs(oc, U, dt=dt) if cells is None else O.rhs_cells(oc, U, cells, dt=dt)
     worst = np.zeros(U.shape[0])
@@ -63,7 +67,9 @@ def roundoff_floor(oc, U, dt, cells=None, trials=2, seed=1):
         Up = U * (1.0 + rng.choice([-1.0, 1.0], size=U.shape) * 2.0 ** -53)
         Rp = O.rhs(oc, Up, dt=dt) if cells is None else O.rhs_cells(oc, Up, cells, dt=dt)
         worst = np.maximum(worst, comp_rel(Rp, R))
-    return worst
+    with O.contracted():
+        Rc = O.rhs(oc, U, dt=dt) if cells is None else O.rhs_cells(oc, U, cells, dt=dt)
+    return np.maximum(worst, comp_rel(Rc, R))
 
 
 def oracle_cfg(case, **kw):
