@@ -26,8 +26,9 @@ PERIODIC, ZERO_GRADIENT, SYMMETRY = 0, 1, 2
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _FMA_PATH = os.path.join(_HERE, "liboracle_fma.so")
+_ULP_PATH = os.path.join(_HERE, "liboracle_ulp.so")
 _lib = None
-_fma_lib = None
+_variants = {}
 
 
 def build() -> None:
@@ -35,6 +36,7 @@ def build() -> None:
     multiply-add contraction (liboracle_fma.so, used only to calibrate round-off floors)."""
     subprocess.run(["make", "-s", "-C", _HERE, "-B", "liboracle.so"], check=True)
     subprocess.run(["make", "-s", "-C", _HERE, "-B", "fma", f"FMA_OUT={_FMA_PATH}"], check=True)
+    subprocess.run(["make", "-s", "-C", _HERE, "-B", "ulp", f"ULP_OUT={_ULP_PATH}"], check=True)
 
 
 class _Cfg(ctypes.Structure):
@@ -128,23 +130,30 @@ def lib():
 
 
 @contextlib.contextmanager
-def contracted():
-    """Within the block every oracle call runs the same source built with multiply-add
-    contraction (liboracle_fma.so): a second, equally valid rounding of every
-    operation, whose difference from the reference build is the oracle's own
-    round-off floor (including intermediate roundings that a one-ulp move of the
-    input does not reach)."""
-    global _lib, _fma_lib
+def variant(kind: str):
+    """Within the block every oracle call runs a calibration build of the same
+    source: kind "fma" -- multiply-add contraction (every intermediate rounded
+    differently, which a one-ulp move of the input does not reach); kind "ulp" --
+    every exp, pow, tanh, atanh, cosh and sinh result one unit in the last place
+    higher (another correct math library's rounding).  Their differences from the
+    reference build are the oracle's own round-off floor."""
+    global _lib
+    path, target, var = {"fma": (_FMA_PATH, "fma", "FMA_OUT"), "ulp": (_ULP_PATH, "ulp", "ULP_OUT")}[kind]
     saved = lib()
-    if _fma_lib is None:
-        if not os.path.exists(_FMA_PATH):
-            subprocess.run(["make", "-s", "-C", _HERE, "-B", "fma", f"FMA_OUT={_FMA_PATH}"], check=True)
-        _fma_lib = _load(_FMA_PATH)
-    _lib = _fma_lib
+    if kind not in _variants:
+        if not os.path.exists(path):
+            subprocess.run(["make", "-s", "-C", _HERE, "-B", target, f"{var}={path}"], check=True)
+        _variants[kind] = _load(path)
+    _lib = _variants[kind]
     try:
         yield
     finally:
         _lib = saved
+
+
+def contracted():
+    """variant("fma")."""
+    return variant("fma")
 
 
 def _load(path):

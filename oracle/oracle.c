@@ -53,6 +53,20 @@
 #include <omp.h>
 #endif
 
+#ifdef ORC_TRANSCENDENTAL_ULP
+/* Calibration build only (see the Makefile's target ulp): every result of the
+ * non-correctly-rounded library functions moved up by one unit in the last place,
+ * as another correct math library may round it.  The reference build does not
+ * define this. */
+static double orc_up1(double x) { return nextafter(x, INFINITY); }
+#define exp(x) orc_up1((exp)(x))
+#define pow(x, y) orc_up1((pow)(x, y))
+#define tanh(x) orc_up1((tanh)(x))
+#define atanh(x) orc_up1((atanh)(x))
+#define cosh(x) orc_up1((cosh)(x))
+#define sinh(x) orc_up1((sinh)(x))
+#endif
+
 enum { M_EULER = 0, M_NS = 1, M_DIM = 2 };
 enum { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_SYMMETRY = 2 };
 

@@ -37,7 +37,7 @@ def test_json_line_contract(monkeypatch, capsys, extra):
     assert d["value"] == pytest.approx(cells * 3 / (d["ms_per_step"] * 1e-3), rel=1e-9)
     r = d["roofline"]
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
-    assert r["peak"] == (78.6 if d["dtype"] == "f64" else 157.3)
+    assert r["peak"] == 78.6      # FP64 vector; FP32 without packed operations issues at the same rate
     assert r["achieved"] == pytest.approx(r["flops_per_cell"] * cells / (d["stage_ms"]["mean"] * 1e-3) / 1e12,
                                           rel=1e-9)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-12)

@@ -323,4 +323,13 @@ def test_full_size_post_contact_limiters(opt):
     tol = np.maximum(1e-12, 2.0 * floor)
     print(f"[limiters] full size: R rel err {np.array2string(err, precision=2)} floor "
           f"{np.array2string(floor, precision=2)}", flush=True)
+    Rk, ck = Rh[:, cells][:, keep], cells[keep]
+    for m in range(sc.ncomp):
+        if err[m] > tol[m]:
+            d = np.abs(Rk[m] - Ro[m, keep])
+            for w in np.argsort(d)[-4:]:
+                c = int(ck[w])
+                a = Uh[6].reshape(-1)[c] if sc.ncomp == 7 else 0.0
+                print(f"  comp {m} cell {c} (i={c % nx}, j={(c // nx) % ny}, k={c // (nx * ny)}) alpha1 {a:.6e} "
+                      f"gpu={Rk[m, w]:.17e} oracle={Ro[m, keep][w]:.17e}", flush=True)
     assert np.all(err <= tol), (err, floor)
