@@ -237,16 +237,20 @@ def run_oracle_baseline(n: int, model: int) -> dict:
 
 
 def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: int = 2402,
-                low_rate: float = 20.0, low_n: int = 80) -> dict:
+                low_rate: float = 20.0, low_n: int = 80, fill: int | None = 768, use_graph: bool = True,
+                policy: str = "srpt", backlog: int | None = 8) -> dict:
     """Serving benchmark: a seeded Poisson stream of independent 3-D Riemann problems
     (single- and two-phase, grids 64^3 .. 256x128x128, 50 RK3 steps each, FP32, CFL 0.5),
-    served by continuous batching (graph replay) and one request at a time; at the
-    offered rate of the workload (above what one GPU sustains, so latencies are
-    queueing-dominated) and at a lower rate both paths can sustain."""
+    served by continuous batching (graph replay; admission by memory and, with fill, by
+    GPU fill: a request joins the running batch while the batch's stage workgroups are
+    below the budget) and one request at a time; at the offered rate of the workload
+    (above what one GPU sustains, so latencies are queueing-dominated) and at a lower
+    rate both paths can sustain."""
     from paper_2402_05193_amd import serving as SV
     from paper_2402_05193_amd import workloads as WL
 
-    srv = SV.Server(pool_bytes=int(pool_gib * (1 << 30)), max_batch=max_batch, use_graph=True)
+    srv = SV.Server(pool_bytes=int(pool_gib * (1 << 30)), max_batch=max_batch, use_graph=use_graph,
+                    fill_workgroups=fill, policy=policy, backlog=backlog)
     # warm-up: every kernel variant once on both paths (tiny grids)
     warm = lambda: [SV.job_from_request(WL.riemann_request(i, seed + 1, grids=((16, 16, 16),), steps=2), 0.0)
                     for i in range(6)]
@@ -271,7 +275,10 @@ def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: 
     srv.close()
     out = {"workload": f"Poisson stream of planar 3-D Riemann problems (Euler / five-equation air-helium, "
                        f"grids {list(WL.SERVING_GRIDS)}), 50 TVD-RK3 steps each at CFL 0.5, FP32, limiters on",
-           "max_batch": max_batch, "pool_gib": pool_gib, "offered": main}
+           "max_batch": max_batch, "pool_gib": pool_gib, "fill_workgroups": fill, "policy": policy,
+           "backlog": backlog,
+           "offered": main,
+           "graphs_cached": srv.batch.graph_count()}
     if low is not None:
         out["sustainable"] = low
     out["p50_latency_s"] = main["batched"]["p50_latency_s"]
@@ -371,13 +378,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of known size first (for HBM counter scaling)")
-    ap.add_argument("--serve-requests", type=int, default=160,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving benchmark (0: skip it)")
+    ap.add_argument("--serve-fill", type=int, default=768,
+                    help="a request joins the running batch while the batch has fewer stage workgroups than "
+                         "this (0: whenever a slot and memory are free); 768 = the FP32 stage workgroups resident "
+                         "on 256 CUs at once")
+    ap.add_argument("--serve-only", action="store_true", help="run the serving benchmark alone and print its JSON")
+    ap.add_argument("--serve-eager", action="store_true", help="batched steps without graph replay")
+    ap.add_argument("--serve-backlog", type=int, default=8,
+                    help="srpt: beyond this many resident or queued requests every resident request steps "
+                         "(0: keep the fill budget at any load)")
+    ap.add_argument("--serve-policy", choices=["srpt", "fcfs"], default="srpt",
+                    help="srpt: each step advances the resident requests with the least remaining work that fit "
+                         "the fill budget; fcfs: requests join in arrival order and stay until done")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-batch", type=int, default=32)
     ap.add_argument("--serve-pool-gib", type=float, default=12.0)
     ap.add_argument("--serve-low-rate", type=float, default=20.0, help="arrival rate of the second stream")
-    ap.add_argument("--serve-low-requests", type=int, default=80, help="requests of the second stream (0: skip)")
+    ap.add_argument("--serve-low-requests", type=int, default=200, help="requests of the second stream (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -391,6 +410,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serve_only:
+        res = run_serving(args.serve_requests, args.serve_rate, args.serve_max_batch, args.serve_pool_gib,
+                          low_rate=args.serve_low_rate, low_n=args.serve_low_requests,
+                          fill=args.serve_fill if args.serve_fill > 0 else None, use_graph=not args.serve_eager,
+                          policy=args.serve_policy, backlog=args.serve_backlog if args.serve_backlog > 0 else None)
+        print(json.dumps({"serving": res}), flush=True)
+        return
     model = {"ns": S.NS, "euler": S.EULER, "dim": S.DIM}[args.model]
     dtype = S.F64 if args.dtype == "f64" else S.F32
     if model == S.DIM:
@@ -557,7 +583,10 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_max_batch,
                                      args.serve_pool_gib, low_rate=args.serve_low_rate,
-                                     low_n=args.serve_low_requests)
+                                     low_n=args.serve_low_requests,
+                                     fill=args.serve_fill if args.serve_fill > 0 else None,
+                                     use_graph=not args.serve_eager, policy=args.serve_policy,
+                                     backlog=args.serve_backlog if args.serve_backlog > 0 else None)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint_bench()
         print(f"[bench] adjoint: {json.dumps(out['adjoint'])}", flush=True)

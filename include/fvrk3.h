@@ -175,6 +175,11 @@ int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
  * otherwise the same as rhs).  The workspace contents are overwritten. */
 int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, void* stream);
 
+/* Workgroups of one fused stage launch of the problem (alone, or its share of a
+ * batched launch); a measure of how much of the GPU the problem fills (each
+ * CU holds two FP64 or three FP32 stage workgroups at a time). */
+int stage_workgroups(const fv_config* cfg, int32_t* out);
+
 /* Bytes of the limiter decision record of rhs_flags: one byte per cell face,
  * (nx+1) ny nz + nx (ny+1) nz + nx ny (nz+1). */
 int limiter_flag_bytes(const fv_config* cfg, size_t* out);
@@ -311,17 +316,29 @@ int batch_destroy(fv_batch* b);
  * workspaces.  fresh (optional, n flags): members whose time stepping starts
  * now: their first dt is computed from U and their simulated time set to 0.
  * The table upload is stream-ordered: work enqueued earlier still runs on the
- * previous membership.  Invalidates a captured graph. */
+ * previous membership.  Captured graphs stay valid (they read the membership
+ * from the table). */
 int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, void* const* ws, const int32_t* fresh,
               void* stream);
 
-/* nsteps TVD-RK3 steps (Sec. 3.4) of every member, CFL mode. */
+/* nsteps TVD-RK3 steps (Sec. 3.4) of every member, CFL mode.  A group with a
+ * single member runs the single-problem stage kernel with that member's
+ * arguments (the same arithmetic). */
 int batch_step(fv_batch* b, int32_t nsteps, void* stream);
 
-/* As batch_step, through a HIP graph of nsteps steps captured on first use and
- * replayed while the membership, nsteps and stream stay the same.  stream must
- * not be the default (NULL) stream. */
+/* As batch_step, through a HIP graph of nsteps steps.  The graph's kernels read
+ * the membership from the device table, and their grids are the groups'
+ * workgroup counts rounded up to a multiple of an eighth of their power-of-two
+ * floor (spare workgroups return at once), so one captured graph serves every
+ * membership with the same (model, precision, limiter) groups and rounded grids:
+ * graphs are cached per batch under that key, nsteps and the stream (at most 16,
+ * least recently used dropped) and captured on a miss.  stream must not be the
+ * default (NULL) stream; the graph runs on the stream it was captured on.  When
+ * every group has a single member the steps run as batch_step (no graph). */
 int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream);
+
+/* Number of step graphs the batch holds (diagnostics). */
+int batch_graph_count(const fv_batch* b);
 
 /* Thread-local message of the last failure ("" if none). */
 const char* last_error(void);

@@ -50,6 +50,21 @@ size_t state_bytes(const fv_config* c)
 #ifndef FV_TARGET_WORKGROUPS_F32
 #define FV_TARGET_WORKGROUPS_F32 4096
 #endif
+// z chunk of a workgroup (planes): at least FV_MIN_ZCHUNK, unless the launch would then
+// have fewer workgroups than the GPU holds at once (2 FP64 or 3 FP32 stage workgroups
+// on each of the 256 CUs); then halved down to FV_SMALLEST_ZCHUNK.  Each chunk repeats
+// the z-march's start (window loads, two z-only steps; two in-plane warm-up planes for
+// the viscous model), which costs more than idle CUs only once they are all busy.
+// Measured per stage (ms; chunk 16 / 8 / 4): NS FP64 128^3 0.318 / 0.332 / 0.355,
+// 64^3 0.225 / 0.122 / 0.075; five-equation FP32 256x64x64 0.222 / 0.143 / 0.139,
+// 128x32x32 0.222 / 0.115 / 0.064; Euler FP32 64^3 0.133 / 0.072 / 0.044.
+#ifndef FV_MIN_ZCHUNK
+#define FV_MIN_ZCHUNK 16
+#endif
+#ifndef FV_SMALLEST_ZCHUNK
+#define FV_SMALLEST_ZCHUNK 4
+#endif
+constexpr int RESIDENT_CUS = 256;
 
 constexpr size_t SCALAR_BYTES = 256;  // dt, inverse-dt max, time accumulator, check words
 
@@ -190,7 +205,11 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
     int nch = (int)((target + tiles - 1) / tiles);
     if (nch < 1) nch = 1;
     int zc = (c->nz + nch - 1) / nch;
-    if (zc < 16) zc = 16 < c->nz ? 16 : c->nz;
+    if (zc < FV_MIN_ZCHUNK) {
+        zc = FV_MIN_ZCHUNK < c->nz ? FV_MIN_ZCHUNK : c->nz;
+        const long long slots = (long long)RESIDENT_CUS * (f64 ? 2 : 3);
+        while (zc / 2 >= FV_SMALLEST_ZCHUNK && tiles * ((c->nz + zc - 1) / zc) < slots) zc /= 2;
+    }
     a.zchunk = zc;
     a.nchunks = (c->nz + zc - 1) / zc;
     g.nblocks = (int)(tiles * a.nchunks);
@@ -422,6 +441,18 @@ int limiter_flag_bytes(const fv_config* cfg, size_t* out)
     long long off[3], total;
     flag_offsets(cfg, off, &total);
     *out = (size_t)total;
+    return FV_OK;
+}
+
+int stage_workgroups(const fv_config* cfg, int32_t* out)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if (!out) return fail(FV_ENULL, "out is NULL");
+    fv::LaunchGeom g;
+    if (cfg->dtype == FV_F64) (void)stage_args<double>(cfg, g);
+    else (void)stage_args<float>(cfg, g);
+    *out = g.nblocks;
     return FV_OK;
 }
 
@@ -745,18 +776,63 @@ const char* last_error(void) { return g_err; }
 // A batch is a set of independent problems advanced together: every RK stage
 // is one launch per (model, precision, limiter) group whose workgroups are
 // spread over the group's problems through a device table.
+//
+// Table layout (device, caller-owned), for a batch of capacity C: one region per
+// group present, in the order of the group id (model, precision, limiter), each
+//   [header: int count][int first[C+1]][StageArgs args[C] for stage 1][.. stage 2][.. stage 3]
+// then [header: int n][BatchScalars scal[C]].  The kernels read the counts from the
+// table, so a captured step serves any membership with the same groups and grid
+// sizes: graphs are cached by (groups, bucketed grid sizes, steps, stream) and
+// replayed after later batch_set calls.
 
 namespace {
 
 constexpr int MAX_GROUPS = 12;   // 3 models x 2 precisions x 2 limiter settings
 constexpr size_t TAB_ALIGN = 256;
+constexpr int MAX_GRAPHS = 16;   // cached step graphs per batch
 
 size_t align_up(size_t v) { return (v + TAB_ALIGN - 1) & ~(TAB_ALIGN - 1); }
 
 struct BatchGroup {
-    int model, dtype, pos, count, nblocks;
-    size_t first_off, args_off[3];  // byte offsets in the device table
+    int gid, model, dtype, pos, count, nblocks;
+    size_t hdr_off, first_off, args_off[3];  // byte offsets in the device table
+    // a group of one member runs the single-problem stage kernel with these arguments
+    // (the same body: the same results, without the table indirection)
+    fv::StageArgs<double> solo_d[3];
+    fv::StageArgs<float> solo_f[3];
 };
+
+struct GraphEntry {
+    std::vector<long long> key;  // (group id, bucketed grid) per group, then steps
+    hipStream_t stream;
+    hipGraphExec_t exec;
+    unsigned long long last_use;
+};
+
+size_t args_bytes(int capacity) { return align_up((size_t)capacity * sizeof(fv::StageArgs<double>)); }
+
+size_t region_bytes(int capacity)
+{
+    return TAB_ALIGN + align_up(sizeof(int) * (size_t)(capacity + 1)) + 3 * args_bytes(capacity);
+}
+
+size_t table_bound(int capacity)
+{
+    return (size_t)MAX_GROUPS * region_bytes(capacity) + TAB_ALIGN +
+           align_up(sizeof(fv::BatchScalars) * (size_t)capacity);
+}
+
+// grid of a captured stage launch: the group's workgroups rounded up to a multiple of
+// an eighth of their power-of-two floor (at most 12.5 % spare workgroups, which
+// return at once), so that memberships of similar size share a graph
+int grid_bucket(int nb)
+{
+    if (nb <= 8) return nb;
+    int q = 1;
+    while (q * 2 <= nb) q *= 2;
+    const int step = q / 8;
+    return (nb + step - 1) / step * step;
+}
 
 }  // namespace
 
@@ -770,21 +846,12 @@ struct fv_batch {
     int cur = 0;
     int n = 0;
     std::vector<BatchGroup> groups;
-    size_t scal_off = 0;
-    hipGraphExec_t exec = nullptr;
-    int graph_steps = 0;
-    hipStream_t graph_stream = nullptr;
+    size_t scal_hdr_off = 0, scal_off = 0;
+    std::vector<GraphEntry> graphs;
+    unsigned long long uses = 0;
 };
 
 namespace {
-
-size_t table_bound(int capacity)
-{
-    const size_t per = 3 * sizeof(fv::StageArgs<double>) + sizeof(int) + sizeof(fv::BatchScalars);
-    // per group: the block prefix and three argument arrays, each padded to TAB_ALIGN
-    return (size_t)MAX_GROUPS * 4 * TAB_ALIGN + 2 * TAB_ALIGN + (size_t)capacity * per +
-           (size_t)(capacity + MAX_GROUPS) * sizeof(int) + sizeof(fv::BatchScalars) * 4;
-}
 
 template <typename Real>
 void fill_group_args(const fv_config* c, void* U, void* ws, char* img, const BatchGroup& g, int k, int first_block,
@@ -810,36 +877,46 @@ void fill_group_args(const fv_config* c, void* U, void* ws, char* img, const Bat
     *nblocks = geo.nblocks;
 }
 
-int batch_launch_steps(fv_batch* b, int nsteps, hipStream_t st)
+int batch_launch_steps(fv_batch* b, int nsteps, hipStream_t st, bool bucketed)
 {
     const fv::BatchScalars* scal = reinterpret_cast<const fv::BatchScalars*>(b->table + b->scal_off);
+    const int* nmem = reinterpret_cast<const int*>(b->table + b->scal_hdr_off);
     for (int k = 0; k < nsteps; k++) {
         for (int s = 0; s < 3; s++) {
             for (const BatchGroup& g : b->groups) {
+                if (!bucketed && g.count == 1) {
+                    fv::LaunchGeom geo;
+                    geo.nblocks = g.nblocks;
+                    hipError_t e = g.dtype == FV_F64 ? fv::launch_stage<double>(g.model, g.solo_d[s], geo, st)
+                                                     : fv::launch_stage<float>(g.model, g.solo_f[s], geo, st);
+                    if (e != hipSuccess) return hip_fail(e, "batch stage launch (single member)");
+                    continue;
+                }
                 const int* first = reinterpret_cast<const int*>(b->table + g.first_off);
+                const int* count = reinterpret_cast<const int*>(b->table + g.hdr_off);
+                const int nb = bucketed ? grid_bucket(g.nblocks) : g.nblocks;
                 hipError_t e =
                     g.dtype == FV_F64
                         ? fv::launch_batch_stage<double>(g.model, g.pos != 0,
                                                          reinterpret_cast<const fv::StageArgs<double>*>(b->table + g.args_off[s]),
-                                                         first, g.count, g.nblocks, st)
+                                                         first, count, nb, st)
                         : fv::launch_batch_stage<float>(g.model, g.pos != 0,
                                                         reinterpret_cast<const fv::StageArgs<float>*>(b->table + g.args_off[s]),
-                                                        first, g.count, g.nblocks, st);
+                                                        first, count, nb, st);
                 if (e != hipSuccess) return hip_fail(e, "batch stage launch");
             }
         }
-        hipError_t e = fv::launch_batch_dt_finish(scal, b->n, st);
+        hipError_t e = fv::launch_batch_dt_finish(scal, nmem, bucketed ? b->capacity : b->n, st);
         if (e != hipSuccess) return hip_fail(e, "batch dt finish");
     }
     return FV_OK;
 }
 
-void drop_graph(fv_batch* b)
+void drop_graphs(fv_batch* b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-    b->graph_steps = 0;
-    b->graph_stream = nullptr;
+    for (GraphEntry& g : b->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
 }
 
 }  // namespace
@@ -884,7 +961,7 @@ int batch_create(int32_t capacity, void* table, size_t table_bytes, fv_batch** o
 int batch_destroy(fv_batch* b)
 {
     if (!b) return FV_OK;
-    drop_graph(b);
+    drop_graphs(b);
     for (int k = 0; k < 2; k++) {
         if (b->copied[k]) {
             if (b->pending[k]) (void)hipEventSynchronize(b->copied[k]);
@@ -914,39 +991,38 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if (cfgs[i].thinc) return fail(FV_EUNSUPPORTED, "member %d: batches run without THINC", i);
         if (cfgs[i].visc_law != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use constant viscosity", i);
     }
-    // groups in order of first appearance; members keep their order inside a group
-    std::vector<BatchGroup> groups;
+    // groups present, in the order of their id; members keep their order inside a group
+    int gcount[MAX_GROUPS] = {0};
     std::vector<int> gid(n);
     for (int i = 0; i < n; i++) {
-        const int pos = positivity_on(&cfgs[i]) ? 1 : 0;
-        int g = 0;
-        for (; g < (int)groups.size(); g++)
-            if (groups[g].model == cfgs[i].model && groups[g].dtype == cfgs[i].dtype && groups[g].pos == pos) break;
-        if (g == (int)groups.size()) {
-            BatchGroup ng;
-            memset(&ng, 0, sizeof ng);
-            ng.model = cfgs[i].model;
-            ng.dtype = cfgs[i].dtype;
-            ng.pos = pos;
-            groups.push_back(ng);
-        }
-        groups[g].count++;
-        gid[i] = g;
+        gid[i] = cfgs[i].model * 4 + cfgs[i].dtype * 2 + (positivity_on(&cfgs[i]) ? 1 : 0);
+        gcount[gid[i]]++;
     }
-    size_t off = 0;
-    for (BatchGroup& g : groups) {
-        const size_t as = g.dtype == FV_F64 ? sizeof(fv::StageArgs<double>) : sizeof(fv::StageArgs<float>);
-        g.first_off = off;
-        off = align_up(off + sizeof(int) * (size_t)(g.count + 1));
-        for (int s = 0; s < 3; s++) {
-            g.args_off[s] = off;
-            off = align_up(off + as * (size_t)g.count);
-        }
+    std::vector<BatchGroup> groups;
+    int pos_of[MAX_GROUPS];
+    const size_t rb = region_bytes(b->capacity), ab = args_bytes(b->capacity);
+    for (int g = 0; g < MAX_GROUPS; g++) {
+        pos_of[g] = -1;
+        if (!gcount[g]) continue;
+        BatchGroup ng;
+        memset(&ng, 0, sizeof ng);
+        ng.gid = g;
+        ng.model = g / 4;
+        ng.dtype = (g / 2) % 2;
+        ng.pos = g % 2;
+        ng.count = gcount[g];
+        ng.hdr_off = groups.size() * rb;
+        ng.first_off = ng.hdr_off + TAB_ALIGN;
+        for (int s = 0; s < 3; s++)
+            ng.args_off[s] = ng.first_off + align_up(sizeof(int) * (size_t)(b->capacity + 1)) + s * ab;
+        pos_of[g] = (int)groups.size();
+        groups.push_back(ng);
     }
-    const size_t scal_off = off;
-    off = align_up(off + sizeof(fv::BatchScalars) * (size_t)(n > 0 ? n : 1));
-    if (off > b->table_bytes || off > table_bound(b->capacity))
-        return fail(FV_EINVAL, "batch table too small (%zu > %zu)", off, b->table_bytes);
+    const size_t scal_hdr_off = groups.size() * rb;
+    const size_t scal_off = scal_hdr_off + TAB_ALIGN;
+    const size_t end = scal_off + sizeof(fv::BatchScalars) * (size_t)(n > 0 ? n : 1);
+    if (end > b->table_bytes || end > table_bound(b->capacity))
+        return fail(FV_EINVAL, "batch table too small (%zu > %zu)", end, b->table_bytes);
 
     // the staging buffer may still feed an earlier copy
     const int k = b->cur;
@@ -956,33 +1032,43 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         b->pending[k] = false;
     }
     char* img = b->host[k];
-    memset(img, 0, off);
+    memset(img, 0, end);
     std::vector<int> slot(groups.size(), 0), first(groups.size(), 0);
     fv::BatchScalars* sc = reinterpret_cast<fv::BatchScalars*>(img + scal_off);
     for (int i = 0; i < n; i++) {
-        BatchGroup& g = groups[gid[i]];
+        const int p = pos_of[gid[i]];
+        BatchGroup& g = groups[p];
         int nb = 0;
-        if (g.dtype == FV_F64) fill_group_args<double>(&cfgs[i], U[i], ws[i], img, g, slot[gid[i]], first[gid[i]], &nb);
-        else fill_group_args<float>(&cfgs[i], U[i], ws[i], img, g, slot[gid[i]], first[gid[i]], &nb);
-        slot[gid[i]]++;
-        first[gid[i]] += nb;
+        if (g.dtype == FV_F64) fill_group_args<double>(&cfgs[i], U[i], ws[i], img, g, slot[p], first[p], &nb);
+        else fill_group_args<float>(&cfgs[i], U[i], ws[i], img, g, slot[p], first[p], &nb);
+        slot[p]++;
+        first[p] += nb;
         const WsLayout w = ws_layout(&cfgs[i], ws[i]);
         sc[i].inv_max = w.inv_max;
         sc[i].dt = w.dt;
         sc[i].t_acc = w.t_acc;
         sc[i].cfl = cfgs[i].cfl;
     }
-    for (size_t g = 0; g < groups.size(); g++) {
-        reinterpret_cast<int*>(img + groups[g].first_off)[groups[g].count] = first[g];
-        groups[g].nblocks = first[g];
+    for (size_t p = 0; p < groups.size(); p++) {
+        reinterpret_cast<int*>(img + groups[p].hdr_off)[0] = groups[p].count;
+        reinterpret_cast<int*>(img + groups[p].first_off)[groups[p].count] = first[p];
+        groups[p].nblocks = first[p];
+        for (int s = 0; s < 3; s++) {
+            if (groups[p].dtype == FV_F64)
+                groups[p].solo_d[s] = reinterpret_cast<const fv::StageArgs<double>*>(img + groups[p].args_off[s])[0];
+            else
+                groups[p].solo_f[s] = reinterpret_cast<const fv::StageArgs<float>*>(img + groups[p].args_off[s])[0];
+        }
     }
+    reinterpret_cast<int*>(img + scal_hdr_off)[0] = n;
     // kernel attributes before any capture
     for (const BatchGroup& g : groups) {
-        hipError_t e = g.dtype == FV_F64 ? fv::launch_batch_stage<double>(g.model, g.pos != 0, nullptr, nullptr, 0, 0, st)
-                                         : fv::launch_batch_stage<float>(g.model, g.pos != 0, nullptr, nullptr, 0, 0, st);
+        hipError_t e = g.dtype == FV_F64
+                           ? fv::launch_batch_stage<double>(g.model, g.pos != 0, nullptr, nullptr, nullptr, 0, st)
+                           : fv::launch_batch_stage<float>(g.model, g.pos != 0, nullptr, nullptr, nullptr, 0, st);
         if (e != hipSuccess) return hip_fail(e, "batch_set: kernel attributes");
     }
-    hipError_t e = hipMemcpyAsync(b->table, img, off, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(b->table, img, end, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(b->copied[k], st);
     if (e != hipSuccess) return hip_fail(e, "batch_set: table upload");
     b->pending[k] = true;
@@ -999,9 +1085,9 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if (e == hipSuccess) e = fv::launch_reset_max((unsigned long long*)w.t_acc, st);
         if (e != hipSuccess) return hip_fail(e, "batch_set: first dt");
     }
-    drop_graph(b);
     b->groups = groups;
     b->n = n;
+    b->scal_hdr_off = scal_hdr_off;
     b->scal_off = scal_off;
     return FV_OK;
 }
@@ -1011,7 +1097,7 @@ int batch_step(fv_batch* b, int32_t nsteps, void* stream)
     if (!b) return fail(FV_ENULL, "batch is NULL");
     if (nsteps < 0) return fail(FV_EINVAL, "nsteps must be >= 0");
     if (b->n == 0) return FV_OK;
-    return batch_launch_steps(b, nsteps, (hipStream_t)stream);
+    return batch_launch_steps(b, nsteps, (hipStream_t)stream, false);
 }
 
 int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream)
@@ -1021,11 +1107,31 @@ int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream)
     if (!stream) return fail(FV_EINVAL, "graph capture needs a non-default stream");
     if (b->n == 0) return FV_OK;
     hipStream_t st = (hipStream_t)stream;
-    if (!b->exec || b->graph_steps != nsteps || b->graph_stream != st) {
-        drop_graph(b);
+    // one member per group: the single-problem kernels, launched directly (a graph of
+    // them would have to be captured again for every member)
+    bool all_single = true;
+    for (const BatchGroup& g : b->groups) all_single = all_single && g.count == 1;
+    if (all_single) return batch_launch_steps(b, nsteps, st, false);
+    std::vector<long long> key;
+    for (const BatchGroup& g : b->groups) {
+        key.push_back(g.gid);
+        key.push_back(grid_bucket(g.nblocks));
+    }
+    key.push_back(nsteps);
+    GraphEntry* hit = nullptr;
+    for (GraphEntry& ge : b->graphs)
+        if (ge.stream == st && ge.key == key) hit = &ge;
+    if (!hit) {
+        if ((int)b->graphs.size() >= MAX_GRAPHS) {
+            size_t lru = 0;
+            for (size_t i = 1; i < b->graphs.size(); i++)
+                if (b->graphs[i].last_use < b->graphs[lru].last_use) lru = i;
+            (void)hipGraphExecDestroy(b->graphs[lru].exec);
+            b->graphs.erase(b->graphs.begin() + (long)lru);
+        }
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "batch_step_graph: begin capture");
-        const int r = batch_launch_steps(b, nsteps, st);
+        const int r = batch_launch_steps(b, nsteps, st, true);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(st, &graph);
         if (r) {
@@ -1033,18 +1139,27 @@ int batch_step_graph(fv_batch* b, int32_t nsteps, void* stream)
             return r;
         }
         if (e != hipSuccess) return hip_fail(e, "batch_step_graph: end capture");
-        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            b->exec = nullptr;
-            return hip_fail(e, "batch_step_graph: instantiate");
-        }
-        b->graph_steps = nsteps;
-        b->graph_stream = st;
+        if (e != hipSuccess) return hip_fail(e, "batch_step_graph: instantiate");
+        GraphEntry ge;
+        ge.key = key;
+        ge.stream = st;
+        ge.exec = exec;
+        ge.last_use = 0;
+        b->graphs.push_back(ge);
+        hit = &b->graphs.back();
     }
-    hipError_t e = hipGraphLaunch(b->exec, st);
+    hit->last_use = ++b->uses;
+    hipError_t e = hipGraphLaunch(hit->exec, st);
     if (e != hipSuccess) return hip_fail(e, "batch_step_graph: launch");
     return FV_OK;
+}
+
+int batch_graph_count(const fv_batch* b)
+{
+    return b ? (int)b->graphs.size() : 0;
 }
 
 int workspace_time(const fv_config* cfg, const void* ws, double* t, void* stream)

@@ -277,10 +277,10 @@ __global__ void dt_finish_kernel(unsigned long long* inv_max, double cfl, double
     }
 }
 
-__global__ void batch_dt_finish_kernel(const BatchScalars* __restrict__ s, int n)
+__global__ void batch_dt_finish_kernel(const BatchScalars* __restrict__ s, const int* __restrict__ count)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) {
+    if (r < *count) {
         const BatchScalars b = s[r];
         *b.t_acc += *b.dt;
         const double m = __longlong_as_double((long long)*b.inv_max);
@@ -289,10 +289,10 @@ __global__ void batch_dt_finish_kernel(const BatchScalars* __restrict__ s, int n
     }
 }
 
-hipError_t launch_batch_dt_finish(const BatchScalars* s, int n, hipStream_t st)
+hipError_t launch_batch_dt_finish(const BatchScalars* s, const int* count, int max_n, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_dt_finish_kernel, dim3((n + 63) / 64), dim3(64), 0, st, s, n);
+    if (max_n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_dt_finish_kernel, dim3((max_n + 63) / 64), dim3(64), 0, st, s, count);
     return hipGetLastError();
 }
 

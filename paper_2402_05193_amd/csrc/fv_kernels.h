@@ -89,11 +89,12 @@ size_t stage_lds_bytes();
 
 // Fused stage over n independent problems of one model / precision / limiter
 // setting: args[r] describes problem r, whose workgroups are first[r] ..
-// first[r+1]-1 (device arrays); nblocks = first[n].  nblocks 0 only prepares
-// the kernel's attributes (call before stream capture).
+// first[r+1]-1 (device arrays), n = *count (device).  nblocks >= first[n]
+// workgroups are launched (the rest return at once); nblocks 0 only prepares the
+// kernel's attributes (call before stream capture).
 template <typename Real>
-hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
-                              hipStream_t st);
+hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, const int* count,
+                              int nblocks, hipStream_t st);
 
 // Sixth-order central viscous fluxes (fv_visc6.hip), three passes over the
 // state U of the viscous model:
@@ -123,8 +124,9 @@ struct BatchScalars {
     double* t_acc;                // simulated time
     double cfl;
 };
-// for every r < n: t_acc += dt; dt = cfl / inv_max; inv_max = 0
-hipError_t launch_batch_dt_finish(const BatchScalars* s, int n, hipStream_t st);
+// for every r < *count (device): t_acc += dt; dt = cfl / inv_max; inv_max = 0; the
+// launch covers max_n members
+hipError_t launch_batch_dt_finish(const BatchScalars* s, const int* count, int max_n, hipStream_t st);
 
 // Point-wise / reduction kernels (fv_aux.hip)
 struct AuxArgs {

@@ -979,21 +979,30 @@ __global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const S
 
 // Many independent problems in one launch: the workgroups of problem r are
 // first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
-// and limiter setting for every problem of the launch).
+// and limiter setting for every problem of the launch); *count = n, read from the
+// device table so that a captured launch serves any membership (workgroups beyond
+// first[n] return at once).
 template <typename Real, int MODEL, int POS, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, stage_waves<Real>())
-    batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first, const int n)
+    batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first,
+                       const int* __restrict__ count)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int b = (int)blockIdx.x;
-    if (b >= first[n]) return;
+    const int n = *count;
+    if (n <= 0 || b >= first[n]) return;
     int lo = 0, hi = n - 1;  // last r with first[r] <= b
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stage_body<Real, MODEL, POS, REC_WENO_PRIM, VM_CONST, BX, BY, NTH>(args[lo], b - first[lo], smem_raw);
+    // the argument block is read through the constant address space, as the single-problem
+    // kernel reads its kernel-argument segment: the table does not change during the launch,
+    // so the compiler may load its fields with scalar loads wherever it needs them
+    using CArgs = const __attribute__((address_space(4))) StageArgs<Real>;
+    const StageArgs<Real>* pa = (const StageArgs<Real>*)(CArgs*)(args + lo);
+    stage_body<Real, MODEL, POS, REC_WENO_PRIM, VM_CONST, BX, BY, NTH>(*pa, b - first[lo], smem_raw);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1064,7 +1073,8 @@ hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStr
 }
 
 template <typename Real, int MODEL, int POS>
-static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, int n, int nblocks, hipStream_t st)
+static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, const int* count, int nblocks,
+                                    hipStream_t st)
 {
     using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>;
     const size_t lds = TL::bytes();
@@ -1076,24 +1086,29 @@ static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* firs
         attr_set = true;
     }
     if (nblocks <= 0) return hipSuccess;  // attribute set-up only
-    hipLaunchKernelGGL(k, dim3(nblocks), dim3(TILE_NT), lds, st, args, first, n);
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(TILE_NT), lds, st, args, first, count);
     return hipGetLastError();
 }
 
-template <typename Real>
-hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, int n, int nblocks,
+// the batched kernels of one precision and model (instantiated with that model's
+// primitive WENO5-Z family in fv_stage_inst.hip, so that they are compiled with the same
+// code-generation options as the single-problem kernel they share their body with)
+template <typename Real, int MODEL>
+hipError_t launch_batch_model(bool pos, const StageArgs<Real>* args, const int* first, const int* count, int nblocks,
                               hipStream_t st)
 {
+    return pos ? launch_batch_tile<Real, MODEL, 1>(args, first, count, nblocks, st)
+               : launch_batch_tile<Real, MODEL, 0>(args, first, count, nblocks, st);
+}
+
+template <typename Real>
+hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, const int* count,
+                              int nblocks, hipStream_t st)
+{
     switch (model) {
-    case EULER:
-        return pos ? launch_batch_tile<Real, EULER, 1>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, EULER, 0>(args, first, n, nblocks, st);
-    case NS:
-        return pos ? launch_batch_tile<Real, NS, 1>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, NS, 0>(args, first, n, nblocks, st);
-    default:
-        return pos ? launch_batch_tile<Real, DIM, 1>(args, first, n, nblocks, st)
-                   : launch_batch_tile<Real, DIM, 0>(args, first, n, nblocks, st);
+    case EULER: return launch_batch_model<Real, EULER>(pos, args, first, count, nblocks, st);
+    case NS: return launch_batch_model<Real, NS>(pos, args, first, count, nblocks, st);
+    default: return launch_batch_model<Real, DIM>(pos, args, first, count, nblocks, st);
     }
 }
 

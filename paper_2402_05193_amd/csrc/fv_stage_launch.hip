@@ -4,8 +4,10 @@
 
 namespace fv {
 
-// the kernel families live in fv_stage_inst.hip objects
+// the kernel families (and the batched kernels) live in fv_stage_inst.hip objects
 #define FV_EXTERN_REC(R, M)                                                                                    \
+    extern template hipError_t launch_batch_model<R, M>(bool, const StageArgs<R>*, const int*, const int*, int,     \
+                                                        hipStream_t);                                               \
     extern template hipError_t launch_rec<R, M, REC_WENO_PRIM>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
     extern template hipError_t launch_rec<R, M, REC_WENO_CHAR>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
     extern template hipError_t launch_rec<R, M, REC_TENO_PRIM>(const StageArgs<R>&, const LaunchGeom&, hipStream_t); \
@@ -18,8 +20,10 @@ FV_EXTERN_REC(float, NS)
 FV_EXTERN_REC(float, DIM)
 #undef FV_EXTERN_REC
 
-template hipError_t launch_batch_stage<double>(int, bool, const StageArgs<double>*, const int*, int, int, hipStream_t);
-template hipError_t launch_batch_stage<float>(int, bool, const StageArgs<float>*, const int*, int, int, hipStream_t);
+template hipError_t launch_batch_stage<double>(int, bool, const StageArgs<double>*, const int*, const int*, int,
+                                                hipStream_t);
+template hipError_t launch_batch_stage<float>(int, bool, const StageArgs<float>*, const int*, const int*, int,
+                                               hipStream_t);
 
 template hipError_t launch_stage<double>(int, const StageArgs<double>&, const LaunchGeom&, hipStream_t);
 template hipError_t launch_stage<float>(int, const StageArgs<float>&, const LaunchGeom&, hipStream_t);

@@ -96,10 +96,18 @@ class Job:
     admitted: float | None = None
     finish: float | None = None
     result: torch.Tensor | None = None
+    _wg: int | None = None
 
     @property
     def latency(self) -> float:
         return self.finish - self.arrival
+
+    @property
+    def workgroups(self) -> int:
+        """Workgroups of one stage launch of this problem (its share of a batched launch)."""
+        if self._wg is None:
+            self._wg = S.stage_workgroups(self.cfg)
+        return self._wg
 
     @property
     def cell_updates(self) -> int:
@@ -135,7 +143,8 @@ class Server:
     """Owns the arena, the batch handle and the stream the solves run on."""
 
     def __init__(self, pool_bytes: int = 12 << 30, max_batch: int = 32, device="cuda", use_graph: bool = True,
-                 max_inflight: int = 2):
+                 max_inflight: int = 2, fill_workgroups: int | None = None, policy: str = "fcfs",
+                 backlog: int | None = None):
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)  # default priority
         self.arena = torch.empty(int(pool_bytes) // ALIGN * ALIGN, dtype=torch.uint8, device=self.device)
@@ -144,6 +153,22 @@ class Server:
         self.batch = S.Batch(self.max_batch, self.device)
         self.use_graph = use_graph
         self.max_inflight = max_inflight
+        # admission by GPU fill: a request joins the running batch only while the batch's
+        # stage workgroups are below this budget (the GPU is not yet full), or when the
+        # batch is empty; None admits whenever a slot and memory are free
+        self.fill_workgroups = fill_workgroups
+        # "fcfs": requests join the running batch in arrival order and stay in it until
+        # their last step; "srpt": every admitted request is resident (state and workspace
+        # in the arena) and each step advances the members with the least remaining work
+        # (remaining steps x cells, five-equation cells weighted 1.6) that fit the fill
+        # budget -- the others wait between steps, which changes nothing in their results
+        if policy not in ("fcfs", "srpt"):
+            raise ValueError("policy must be 'fcfs' or 'srpt'")
+        self.policy = policy
+        # srpt: with more than this many resident requests (a backlog) the fill budget is
+        # lifted and every resident request (up to max_batch) steps together, for
+        # throughput; None keeps the budget at any load
+        self.backlog = backlog
 
     # ---------------------------------------------------------------- memory
     @staticmethod
@@ -186,6 +211,8 @@ class Server:
 
     def run_batched(self, jobs: list[Job], keep_results: bool = False) -> RunStats:
         """Serve the jobs (sorted by arrival) with continuous batching."""
+        if self.policy == "srpt":
+            return self._run_srpt(jobs, keep_results)
         jobs = sorted(jobs, key=lambda j: j.arrival)
         n = len(jobs)
         queue: deque[Job] = deque()
@@ -216,6 +243,9 @@ class Server:
                 nxt += 1
             while queue and len(active) < self.max_batch:
                 j = queue[0]
+                if self.fill_workgroups is not None and active:
+                    if sum(x.workgroups for x in active) >= self.fill_workgroups:
+                        break
                 if not self._place(j):
                     break
                 queue.popleft()
@@ -259,6 +289,101 @@ class Server:
         retire(True)
         self.batch.set([], stream=self.stream)
         return self._stats("batched-graph" if self.use_graph else "batched", jobs, max_seen, steps)
+
+    @staticmethod
+    def _remaining_work(j: Job) -> float:
+        return (j.steps - j.steps_done) * j.cfg.ncells * (1.6 if j.cfg.model == S.DIM else 1.0)
+
+    def _run_srpt(self, jobs: list[Job], keep_results: bool) -> RunStats:
+        """Continuous batching with every admitted request resident and each step
+        given to the least remaining work that fits the fill budget."""
+        jobs = sorted(jobs, key=lambda j: j.arrival)
+        n = len(jobs)
+        queue: deque[Job] = deque()
+        resident: list[Job] = []
+        fresh: set[int] = set()
+        inflight: deque = deque()
+        members: list[Job] = []
+        nxt = done = 0
+        max_seen = steps = 0
+        ref, t0 = self._start_clock()
+
+        def retire(block: bool):
+            nonlocal done
+            while inflight and (block or len(inflight) > self.max_inflight or inflight[0][0].query()):
+                ev, fin = inflight.popleft()
+                ev.synchronize()
+                t = ref.elapsed_time(ev) * 1e-3
+                for j in fin:
+                    j.finish = t
+                    self._free(j)
+                    done += 1
+                block = False
+
+        while done < n:
+            now = time.perf_counter() - t0
+            while nxt < n and jobs[nxt].arrival <= now:
+                queue.append(jobs[nxt])
+                nxt += 1
+            while queue:
+                j = queue[0]
+                if not self._place(j):
+                    break
+                queue.popleft()
+                j.admitted = now
+                self._init(j)
+                resident.append(j)
+                fresh.add(j.index)
+            if resident:
+                # the members of this step: least remaining work first, within the budget
+                order = sorted(resident, key=self._remaining_work)
+                budget = self.fill_workgroups
+                if self.backlog is not None and len(resident) + len(queue) > self.backlog:
+                    budget = None
+                chosen, wg = [], 0
+                for j in order:
+                    if len(chosen) >= self.max_batch:
+                        break
+                    if chosen and budget is not None and wg >= budget:
+                        break
+                    chosen.append(j)
+                    wg += j.workgroups
+                if [j.index for j in chosen] != [j.index for j in members] or any(j.index in fresh for j in chosen):
+                    members = chosen
+                    self.batch.set([(j.cfg, j.U, j.ws) for j in members],
+                                   fresh=[j.index in fresh for j in members], stream=self.stream)
+                    for j in members:
+                        fresh.discard(j.index)
+                if self.use_graph:
+                    self.batch.step_graph(1, stream=self.stream)
+                else:
+                    self.batch.step(1, stream=self.stream)
+                steps += 1
+                max_seen = max(max_seen, len(members))
+                finished = []
+                for j in members:
+                    j.steps_done += 1
+                    if j.steps_done == j.steps:
+                        finished.append(j)
+                if finished:
+                    for j in finished:
+                        self._finish_job(j, keep_results)
+                    resident = [j for j in resident if j.steps_done < j.steps]
+                    members = [j for j in members if j.steps_done < j.steps]
+                    self.batch.set([(j.cfg, j.U, j.ws) for j in members], stream=self.stream)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.stream)
+                inflight.append((ev, finished))
+                retire(False)
+            elif inflight:
+                retire(True)
+            elif nxt < n:
+                time.sleep(max(0.0, jobs[nxt].arrival - (time.perf_counter() - t0)))
+            elif queue:
+                raise RuntimeError("a request does not fit in the arena")
+        retire(True)
+        self.batch.set([], stream=self.stream)
+        return self._stats("batched-srpt" + ("-graph" if self.use_graph else ""), jobs, max_seen, steps)
 
     def run_sequential(self, jobs: list[Job], keep_results: bool = False) -> RunStats:
         """Serve the jobs one at a time (arrival order) with the single-problem advance call."""

@@ -29,7 +29,7 @@ EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_t
             "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "advance_noalloc", "rhs_adjoint", "adjoint_workspace_bytes",
             "rk3_step_adjoint", "check_state", "workspace_time",
             "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
-            "last_error"]
+            "batch_graph_count", "stage_workgroups", "last_error"]
 
 
 class FVError(RuntimeError):
@@ -171,6 +171,8 @@ def lib():
                                 ctypes.POINTER(ctypes.c_int32), vp]
         L.batch_step.argtypes = [vp, ctypes.c_int32, vp]
         L.batch_step_graph.argtypes = [vp, ctypes.c_int32, vp]
+        L.batch_graph_count.argtypes = [vp]
+        L.stage_workgroups.argtypes = [cp, ctypes.POINTER(ctypes.c_int32)]
         L.last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("last_error",):
@@ -414,6 +416,14 @@ def config_from_case(case, dtype: int = F64, **over) -> Config:
     return Config(dtype=dtype, **kw)
 
 
+def stage_workgroups(cfg: Config) -> int:
+    """Workgroups of one fused stage launch of the problem."""
+    c = cfg.c_struct()
+    out = ctypes.c_int32(0)
+    _check(lib().stage_workgroups(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
 def workspace_time(cfg: Config, ws: torch.Tensor, stream=None) -> float:
     """Simulated time held in a workspace (synchronises the stream)."""
     c = cfg.c_struct()
@@ -462,6 +472,10 @@ class Batch:
 
     def step_graph(self, nsteps: int = 1, stream=None):
         _check(lib().batch_step_graph(self._h, int(nsteps), _stream(stream)))
+
+    def graph_count(self) -> int:
+        """Step graphs cached by the batch (they survive membership changes)."""
+        return lib().batch_graph_count(self._h)
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -44,6 +44,17 @@ def mixed_jobs(steps=8):
             job(4, S.F64, SMALL_GRIDS[3], steps, two_phase=True)]
 
 
+def grouped_jobs(steps=8):
+    """Members that share (model, precision, limiter) groups: batched launches of
+    several problems (a group of one member runs the single-problem kernel)."""
+    return [job(0, S.F32, SMALL_GRIDS[0], steps, two_phase=False),
+            job(1, S.F32, SMALL_GRIDS[1], steps, two_phase=False),
+            job(2, S.F32, SMALL_GRIDS[2], steps, two_phase=True),
+            job(3, S.F32, SMALL_GRIDS[3], steps, two_phase=True),
+            tgv_job(4, steps=steps),
+            job(5, S.F64, SMALL_GRIDS[2], steps, two_phase=False)]
+
+
 def allocate(j):
     j.U = S.empty_state(j.cfg)
     j.ws = S.workspace(j.cfg)
@@ -111,8 +122,8 @@ def test_batch_graph_replays_equal_eager_steps():
     """The captured graph, replayed several times with eager work and
     synchronisations between the replays, matches the eager batched steps
     after every replay."""
-    eager = mixed_jobs()
-    graph = mixed_jobs()
+    eager = grouped_jobs()
+    graph = grouped_jobs()
     for j in eager + graph:
         allocate(j)
     stream = torch.cuda.Stream()
@@ -129,6 +140,58 @@ def test_batch_graph_replays_equal_eager_steps():
             for a, g in zip(eager, graph):
                 assert_bitwise(g.U, a.U, f"replay {rep}, member {a.index}")
         assert float(scratch[0]) == 4.0
+        be.close()
+        bg.close()
+
+
+def test_batch_graphs_survive_membership_changes():
+    """Members join and leave at different steps; one batch steps through graph
+    replays, another eagerly.  The graphs read the membership from the table, so
+    they are reused across batch_set calls (fewer graphs than memberships), and
+    every member ends bitwise equal in both batches (and to its solo run)."""
+    eager = grouped_jobs(steps=8)
+    graph = grouped_jobs(steps=8)
+    join_at = {0: 0, 2: 0, 5: 0, 1: 3, 3: 3, 4: 5}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        be, bg = S.Batch(8), S.Batch(8)
+        active = {"e": [], "g": []}
+        done, step, sets = 0, 0, 0
+        while done < len(eager):
+            changed = step == 0
+            fresh = set()
+            for je, jg in zip(eager, graph):
+                if join_at[je.index] == step:
+                    allocate(je)
+                    allocate(jg)
+                    active["e"].append(je)
+                    active["g"].append(jg)
+                    fresh.add(je.index)
+                    changed = True
+            if changed:
+                for key, b in (("e", be), ("g", bg)):
+                    b.set([(j.cfg, j.U, j.ws) for j in active[key]], fresh=[j.index in fresh for j in active[key]],
+                          stream=stream)
+                sets += 1
+            be.step(1, stream=stream)
+            bg.step_graph(1, stream=stream)
+            step += 1
+            for key in ("e", "g"):
+                for j in active[key]:
+                    j.steps_done += 1
+            left = [j for j in active["e"] if j.steps_done == j.steps]
+            if left:
+                done += len(left)
+                for key, b in (("e", be), ("g", bg)):
+                    active[key] = [j for j in active[key] if j.steps_done < j.steps]
+                    b.set([(j.cfg, j.U, j.ws) for j in active[key]], stream=stream)
+                sets += 1
+        stream.synchronize()
+        print(f"[serving] {sets} memberships, {bg.graph_count()} graphs captured", flush=True)
+        assert 1 <= bg.graph_count() < sets
+        for je, jg in zip(eager, graph):
+            assert_bitwise(jg.U, je.U, f"member {je.index} graph vs eager")
+            assert_bitwise(jg.U, alone(jg, jg.steps), f"member {jg.index} graph vs alone")
         be.close()
         bg.close()
 
@@ -170,16 +233,19 @@ def test_batched_fp64_members_follow_the_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_server_results_same_alone_and_in_the_mix(use_graph):
-    """Continuous batching with admission by memory: an arena that holds only a
-    few requests, requests arriving while others run; every result equals the
-    request's solo result bitwise, and so does the one-at-a-time path's."""
+@pytest.mark.parametrize("use_graph,fill,policy", [(False, None, "fcfs"), (True, None, "fcfs"), (True, 40, "fcfs"),
+                                                   (True, 40, "srpt"), (False, None, "srpt")])
+def test_server_results_same_alone_and_in_the_mix(use_graph, fill, policy):
+    """Continuous batching with admission by memory (and by GPU fill), in arrival
+    order or least remaining work first (members paused between steps): an arena
+    that holds only a few requests, requests arriving while others run; every
+    result equals the request's solo result bitwise, and so does the
+    one-at-a-time path's."""
     jobs = [job(i, S.F32 if i % 3 else S.F64, steps=6 + i % 3) for i in range(9)]
     for k, j in enumerate(jobs):
         j.arrival = 0.002 * k
     biggest = max(SV.Server.job_bytes(j.cfg) for j in jobs)
-    srv = SV.Server(pool_bytes=3 * biggest, max_batch=4, use_graph=use_graph)
+    srv = SV.Server(pool_bytes=3 * biggest, max_batch=4, use_graph=use_graph, fill_workgroups=fill, policy=policy)
     st = srv.run_batched(jobs, keep_results=True)
     assert st.n == len(jobs) and st.max_batch_seen <= 4
     assert all(j.finish >= j.arrival for j in jobs)
