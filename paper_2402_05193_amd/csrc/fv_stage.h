@@ -147,6 +147,10 @@ struct Tile {
     // THINC: d(psi)/dz at the plane for the tile and its 1-cell ring
     static constexpr int AZ_SIZE = THINC ? (BX + 2) * (BY + 2) : 0;
     static constexpr int NRING = 2 * BX + 2 * BY + 4;
+    // THINC in FP32: psi of each 1-cell ring cell at two consecutive planes (slot =
+    // plane & 1), carried by the thread that owns the ring cell
+    static constexpr bool PSI_CARRY = THINC && sizeof(Real) == 4;
+    static constexpr int PSQ_SIZE = PSI_CARRY ? 2 * NRING : 0;
     // per-thread x/y partial sums of R for planes s-2 / s-1 (two slots); the
     // five-equation model (LDS budget) keeps even planes in one LDS slot and odd planes
     // in registers
@@ -155,7 +159,7 @@ struct Tile {
     static constexpr int ACC_SIZE = ACC_LDS ? 2 * NC * NCELL : (ACC_HALF ? NC * NCELL : 0);
     static constexpr size_t bytes()
     {
-        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE + AZ_SIZE);
+        return sizeof(Real) * (size_t)(WP_SIZE + FB_SIZE + UH_SIZE + DZ_SIZE + DT_SIZE + ACC_SIZE + AZ_SIZE + PSQ_SIZE);
     }
 };
 
@@ -190,6 +194,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     Real* DT = DZX + TL::DZ_SIZE;   // [2][region]     in-plane tangential derivatives
     Real* ACC = DT + TL::DT_SIZE;   // [2][NC][NCELL]  x/y partial sums of R
     Real* AZ = ACC + TL::ACC_SIZE;  // [BY+2][BX+2]    THINC: d(psi)/dz, tile and 1-cell ring
+    Real* PSQ = AZ + TL::AZ_SIZE;   // [2][NRING]      THINC FP32: psi of the ring cells, two planes
 
     const Material<Real> mat = a.mat;
     const Tolerances<Real> tol = a.tol;
@@ -224,11 +229,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         load_cell<Real>(a, a.Uk, gi, gj, gk, u, NC, V, interior_xy);
         cons_to_prim<Real, MODEL>(mat, u, w);
     };
-    auto stage_w = [&](int i, int j, const Real* w, Real psi) {
+    auto stage_w = [&](int i, int j, const Real* w, Real psi, bool with_psi = true) {
 #pragma unroll
         for (int f = 0; f < NC; f++) wp(f, i, j) = w[f];
         if constexpr (VISC) wp(NC, i, j) = w[P] * rcp(w[0]);  // T = p / rho
-        if constexpr (THINC) wp(NC, i, j) = psi;
+        if constexpr (THINC) {
+            if (with_psi) wp(NC, i, j) = psi;
+        }
     };
 
     // reconstruction variant: WENO5-Z of primitive variables per cell (both faces of a
@@ -279,6 +286,45 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     const Real lamy = Real(2 * a.ndim) * dt * idy;
     const Real lamz = Real(2 * a.ndim) * dt * idz;
 
+    // THINC: the 1-cell ring cell of one of the highest-numbered threads, for d(psi)/dz
+    // of the ring.  FP32 (PSI_CARRY): these threads also stage the ring's psi in the
+    // plane, and psi of the cell at planes s-1 and s is carried in PSQ from the two
+    // previous steps, so each step evaluates it once (0.67 -> 0.56 ms per stage for the
+    // five-equation THINC stage at 256x128x128, with the cheaper psi of FP32); halo
+    // threads evaluate psi only where it is read.  FP64 evaluates psi of the ring at s-1
+    // and s+1 in every step and of every halo cell: the carry, or only the skipped halo
+    // cells and the ring's coordinates set once, measured 1.45 against 1.42 ms there.
+    constexpr bool PSI_CARRY = TL::PSI_CARRY;
+    const int rh = NT - 1 - tid;
+    const bool carry_ring = PSI_CARRY && rh < TL::NRING;
+    int cr_i = 0, cr_j = 0;     // the ring cell (tile coordinates) and its column
+    long long cr_col = 0;
+    auto ring_alpha = [&](int k) {
+        bool fz = false;
+        const int kk = map_index(k, a.nz, a.bc[4], a.bc[5], fz);
+        return a.Uk[6 * a.ncell + (long long)kk * a.ny * a.nx + cr_col];
+    };
+    if (carry_ring) {
+        if (rh < 2 * BY) {
+            cr_j = rh >> 1;
+            cr_i = (rh & 1) ? BX : -1;
+        } else if (rh < 2 * BY + 2 * BX) {
+            const int hh = rh - 2 * BY;
+            cr_i = hh >> 1;
+            cr_j = (hh & 1) ? BY : -1;
+        } else {
+            const int hh = rh - 2 * BY - 2 * BX;
+            cr_i = (hh & 1) ? BX : -1;
+            cr_j = (hh & 2) ? BY : -1;
+        }
+        bool fx = false, fy = false;
+        const int ii = map_index(x0 + cr_i, a.nx, a.bc[0], a.bc[1], fx);
+        const int jj = map_index(y0 + cr_j, a.ny, a.bc[2], a.bc[3], fy);
+        cr_col = (long long)jj * a.nx + ii;
+        PSQ[((s_begin - 1) & 1) * TL::NRING + rh] = thinc_psi(ring_alpha(s_begin - 1));
+        PSQ[(s_begin & 1) * TL::NRING + rh] = thinc_psi(ring_alpha(s_begin));
+    }
+
     for (int s = s_begin; s <= z1 + 1; s++) {
         // own column, plane s+2: for the FP64 single-phase kernels loaded after the step's
         // other loads are issued (its conversion waits for it and would hold them back),
@@ -322,6 +368,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             int hi = 0, hj = 0;
             Real hu[NC];
             int hrefl = 0;
+            // THINC: psi is read on the tile, the 1-cell ring (staged by the ring's
+            // threads with PSI_CARRY) and the second ring's arms; a halo thread evaluates
+            // it only there
+            bool hpsi_needed = true;
             const bool has_halo = tid < TL::NHALO;
             if (has_halo) {
                 const int h = tid;
@@ -329,11 +379,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     hj = h / 6;
                     const int k = h % 6;
                     hi = k < 3 ? k - 3 : BX + k - 3;
+                    if constexpr (PSI_CARRY) hpsi_needed = k == 1 || k == 4;
                 } else if (h < 6 * BY + 6 * BX) {
                     const int hh = h - 6 * BY;
                     hi = hh % BX;
                     const int k = hh / BX;
                     hj = k < 3 ? k - 3 : BY + k - 3;
+                    if constexpr (PSI_CARRY) hpsi_needed = k == 1 || k == 4;
                 } else if constexpr (VISC) {
                     const int hh = h - 6 * BY - 6 * BX;  // 2-deep corners (viscous cross terms)
                     const int ci = hh & 3, cj = hh >> 2;
@@ -343,6 +395,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     const int hh = h - 6 * BY - 6 * BX;  // 1-deep corners (THINC gradient)
                     hi = (hh & 1) ? BX : -1;
                     hj = (hh & 2) ? BY : -1;
+                    if constexpr (PSI_CARRY) hpsi_needed = false;  // a ring cell
                 }
                 hrefl = load_cell_raw<Real>(a, a.Uk, x0 + hi, y0 + hj, s, hu, NC, interior_xy);
             }
@@ -392,11 +445,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // the plane buffer is overwritten below: after a step with x/y phases their
             // barriers already ordered every read of it; after a warm-up step (only the
             // in-plane derivatives read it) a barrier is needed here
-            // THINC: alpha of the 1-cell ring at planes s-1 and s+1 for d(psi)/dz at
-            // plane s (highest-numbered threads), issued with the step's other loads
+            // THINC: alpha of the ring cell at plane s+1 (and s-1 without PSI_CARRY) for
+            // d(psi)/dz at plane s, issued with the step's other loads
             Real ring_am = 0, ring_ap = 0;
             int ring_i = 0, ring_j = 0;
-            if constexpr (THINC) {
+            if constexpr (PSI_CARRY) {
+                if (carry_ring) ring_ap = ring_alpha(s + 1);
+            } else if constexpr (THINC) {
                 const int h = NT - 1 - tid;
                 if (h < TL::NRING) {
                     if (h < 2 * BY) {
@@ -428,19 +483,32 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             if (has_cell) stage_w(tx, ty, win[3 + WO], psw[THINC ? 3 + WO : 0]);
             if constexpr (THINC) {
                 // d(psi)/dz at plane s (second-order central): own column from the
-                // window, the 1-cell ring from memory (highest-numbered threads)
+                // window, the 1-cell ring from PSQ and memory (highest-numbered threads),
+                // which also stage the ring's psi at plane s
                 const Real hz = Real(0.5) * idz;
                 if (has_cell) AZ[(ty + 1) * (BX + 2) + tx + 1] = (psw[4 + WO] - psw[2 + WO]) * hz;
-                if (NT - 1 - tid < TL::NRING)
+                if constexpr (PSI_CARRY) {
+                    if (carry_ring) {
+                        const Real pm = PSQ[((s - 1) & 1) * TL::NRING + rh];
+                        const Real p0 = PSQ[(s & 1) * TL::NRING + rh];
+                        const Real pp = thinc_psi(ring_ap);
+                        AZ[(cr_j + 1) * (BX + 2) + cr_i + 1] = (pp - pm) * hz;
+                        wp(NC, cr_i, cr_j) = p0;
+                        PSQ[((s + 1) & 1) * TL::NRING + rh] = pp;  // the slot of plane s-1
+                    }
+                } else if (NT - 1 - tid < TL::NRING) {
                     AZ[(ring_j + 1) * (BX + 2) + ring_i + 1] = (thinc_psi(ring_ap) - thinc_psi(ring_am)) * hz;
+                }
             }
             if (has_halo) {
                 Real w[NC];
                 apply_reflections(hu, V, hrefl);
                 cons_to_prim<Real, MODEL>(mat, hu, w);
                 Real hpsi = 0;
-                if constexpr (THINC) hpsi = thinc_psi(w[6]);
-                stage_w(hi, hj, w, hpsi);
+                if constexpr (THINC) {
+                    if (hpsi_needed) hpsi = thinc_psi(w[6]);
+                }
+                stage_w(hi, hj, w, hpsi, hpsi_needed);
             }
             if constexpr (VISC) {
                 if (xy) {

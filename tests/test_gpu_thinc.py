@@ -57,8 +57,33 @@ def test_rhs_parity_thinc(name, scheme, recon):
     assert np.abs(Ro - R0).max() > 0
 
 
+def step_floor(oc, U, dt, trials=2, seed=1):
+    """The oracle's round-off floor of one RK3 step's increment, per component: the
+    three calibrations of the RHS floor (a one-ulp move of every input value, the
+    contraction build, every transcendental result one ulp higher) applied to the
+    step.  With THINC the interface normal comes from differences of the smoothed
+    volume fraction psi = alpha^0.1 / (alpha^0.1 + (1 - alpha)^0.1) of neighbouring
+    cells (Sec. 3.7), whose slope 0.1 alpha^-0.9 near a pure phase (alpha ~ 1e-8 in the
+    shock-bubble) turns the round-off of the first stages' nearly pure cells into
+    normals that differ at the 1e-7 level: the step itself is that ill-conditioned."""
+    rng = np.random.default_rng(seed)
+    Uo = O.rk3_step(oc, U, dt)
+    worst = np.zeros(U.shape[0])
+    for _ in range(trials):
+        Up = U * (1.0 + rng.choice([-1.0, 1.0], size=U.shape) * 2.0 ** -53)
+        worst = np.maximum(worst, comp_rel(O.rk3_step(oc, Up, dt) - Up, Uo - U))
+    for kind in ("fma", "ulp"):
+        with O.variant(kind):
+            Uc = O.rk3_step(oc, U, dt)
+        worst = np.maximum(worst, comp_rel(Uc - U, Uo - U))
+    return worst
+
+
 @pytest.mark.parametrize("name", ["dim_sbi", "interface_y", "dim_ragged"])
 def test_rk3_step_parity_thinc(name):
+    """Bar: 1e-10 per component of the increment, or twice the step's own round-off
+    floor where that is larger (the shock-bubble, whose floor is ~6e-7: see
+    step_floor)."""
     case = CASES[name]
     oc = oracle_cfg(case, thinc=1)
     U = O.prim_to_cons(oc, case.W)
@@ -68,8 +93,10 @@ def test_rk3_step_parity_thinc(name):
     Ud = dev(U)
     S.rk3_step(sc, Ud, dt, S.workspace(sc))
     err = comp_rel(host(Ud) - U, Uo - U)
-    print(f"[thinc] rk3 step {name} increment rel err {np.array2string(err, precision=2)}", flush=True)
-    assert np.all(err <= 1e-10), err
+    floor = step_floor(oc, U, dt)
+    print(f"[thinc] rk3 step {name} increment rel err {np.array2string(err, precision=2)} "
+          f"floor {np.array2string(floor, precision=2)}", flush=True)
+    assert np.all(err <= np.maximum(1e-10, 2.0 * floor)), (err, floor)
 
 
 def test_fp32_thinc_error_statement():
