@@ -1,4 +1,5 @@
-"""Build libfvrk3.so (HIP, gfx950) in-tree with hipcc.
+"""Build libfvrk3.so (HIP, gfx950) in-tree with hipcc, and the same sources with a
+second tile shape (libfvrk3_tile32x8.so) for the tile-race check of the tests.
 
 Usage: python -m paper_2402_05193_amd.build
 """
@@ -11,6 +12,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvrk3.so")
+# The stage kernels with 32 x 8 cells per workgroup and 320 threads (the product's are
+# 16 x 16 and 256): every x/y task list, the halo and ring assignments and the z chunks
+# map to threads differently, while each cell's arithmetic does not depend on the tiling,
+# so results equal bitwise to the product's unless the LDS plane or the face buffers race.
+LIB_TILE = os.path.join(HERE, "libfvrk3_tile32x8.so")
+TILE_VARIANT = ("-DTILE_BX=32", "-DTILE_BY=8", "-DTILE_NT=320")
 # (source, defines, extra options): the stage kernels compile per precision, model and
 # reconstruction (0 primitive WENO5-Z, 1 characteristic WENO5-Z, 2 primitive TENO6-A,
 # 3 characteristic TENO6-A) so that the units build in parallel and each family gets
@@ -79,5 +86,12 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
     return out
 
 
+def build_tile_variant(verbose: bool = False) -> str:
+    """The second tile shape (LIB_TILE)."""
+    return build(verbose=verbose, extra=list(TILE_VARIANT), out=LIB_TILE)
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])
+    if not sys.argv[1:]:
+        build_tile_variant(verbose=True)

@@ -7,6 +7,7 @@ this module without it raises immediately -- there is no fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from dataclasses import dataclass, field
@@ -134,51 +135,74 @@ class Config:
 _lib = None
 
 
+def load(path: str):
+    """Open a build of the library at ``path`` and declare its entry points (raises if
+    it has not been built)."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2402_05193_amd.build`")
+    return _declare(ctypes.CDLL(path))
+
+
 def lib():
     """The loaded HIP library (raises if it has not been built)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_05193_amd.build`")
-        L = ctypes.CDLL(LIB_PATH)
-        cp = ctypes.POINTER(_Cfg)
-        vp = ctypes.c_void_p
-        L.fv_ncomp.argtypes = [cp]
-        L.workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
-        L.init_state.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
-                                 ctypes.c_uint64, vp, vp]
-        L.prim_to_cons.argtypes = [cp, vp, vp, vp]
-        L.cons_to_prim.argtypes = [cp, vp, vp, vp]
-        L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
-        L.rhs_ws.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
-        L.limiter_flag_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
-        L.rhs_flags.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp, vp]
-        L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
-        L.rk3_stage3_cfl.argtypes = [cp, vp, vp, vp, vp, vp, vp, vp]
-        L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
-        L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
-        L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
-        L.advance_noalloc.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, vp]
-        L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
-        L.adjoint_workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
-        L.rk3_step_adjoint.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
-        L.check_state.argtypes = [cp, vp, vp, ctypes.POINTER(Report), vp]
-        L.workspace_time.argtypes = [cp, vp, ctypes.POINTER(ctypes.c_double), vp]
-        L.batch_table_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
-        L.batch_create.argtypes = [ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
-        L.batch_destroy.argtypes = [vp]
-        L.batch_set.argtypes = [vp, ctypes.c_int32, cp, ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                ctypes.POINTER(ctypes.c_int32), vp]
-        L.batch_step.argtypes = [vp, ctypes.c_int32, vp]
-        L.batch_step_graph.argtypes = [vp, ctypes.c_int32, vp]
-        L.batch_graph_count.argtypes = [vp]
-        L.stage_workgroups.argtypes = [cp, ctypes.POINTER(ctypes.c_int32)]
-        L.last_error.restype = ctypes.c_char_p
-        for name in EXPORTED:
-            if name not in ("last_error",):
-                getattr(L, name).restype = ctypes.c_int
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def using(L):
+    """Within the block every call of this module goes to the library ``L`` (from
+    ``load``), e.g. a build with another tile shape."""
+    global _lib
+    saved = lib()
+    _lib = L
+    try:
+        yield L
+    finally:
+        _lib = saved
+
+
+def _declare(L):
+    """Declare the argument and result types of every entry point of L."""
+    cp = ctypes.POINTER(_Cfg)
+    vp = ctypes.c_void_p
+    L.fv_ncomp.argtypes = [cp]
+    L.workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+    L.init_state.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                             ctypes.c_uint64, vp, vp]
+    L.prim_to_cons.argtypes = [cp, vp, vp, vp]
+    L.cons_to_prim.argtypes = [cp, vp, vp, vp]
+    L.rhs.argtypes = [cp, vp, vp, ctypes.c_double, vp]
+    L.rhs_ws.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
+    L.limiter_flag_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+    L.rhs_flags.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp, vp]
+    L.rk3_stage.argtypes = [cp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.rk3_stage3_cfl.argtypes = [cp, vp, vp, vp, vp, vp, vp, vp]
+    L.rk3_step.argtypes = [cp, vp, ctypes.c_double, vp, vp]
+    L.compute_dt.argtypes = [cp, vp, vp, vp, vp]
+    L.advance.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
+    L.advance_noalloc.argtypes = [cp, vp, ctypes.c_int32, ctypes.c_double, vp]
+    L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
+    L.adjoint_workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
+    L.rk3_step_adjoint.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
+    L.check_state.argtypes = [cp, vp, vp, ctypes.POINTER(Report), vp]
+    L.workspace_time.argtypes = [cp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.batch_table_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.batch_create.argtypes = [ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.batch_destroy.argtypes = [vp]
+    L.batch_set.argtypes = [vp, ctypes.c_int32, cp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                            ctypes.POINTER(ctypes.c_int32), vp]
+    L.batch_step.argtypes = [vp, ctypes.c_int32, vp]
+    L.batch_step_graph.argtypes = [vp, ctypes.c_int32, vp]
+    L.batch_graph_count.argtypes = [vp]
+    L.stage_workgroups.argtypes = [cp, ctypes.POINTER(ctypes.c_int32)]
+    L.last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("last_error",):
+            getattr(L, name).restype = ctypes.c_int
+    return L
 
 
 def _check(code: int):

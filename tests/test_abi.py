@@ -33,6 +33,18 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
 
 
+def test_tile_variant_exports_every_declared_symbol():
+    """The build with the second tile shape (the GPU tile-race check) is the same
+    boundary; its host-side validation answers like the product's."""
+    from paper_2402_05193_amd import build as B
+    L = S.load(B.LIB_TILE)
+    for name in header_functions():
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value, name
+    with S.using(L):
+        assert call_rhs(cfg(nx=0)) == S.EINVAL
+    assert S.lib() is not L
+
+
 def cfg(**kw):
     base = dict(nx=8, ny=8, nz=8, dx=0.1, dy=0.1, dz=0.1)
     base.update(kw)
