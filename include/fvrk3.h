@@ -102,7 +102,7 @@ typedef struct fv_config {
     int32_t recon;       /* reconstruction variables: 0 primitive (Sec. 3.2 as read
                             here), 1 characteristic (Sec. 3.2 steps 1-4, frozen face
                             state = mean of the two cells, appendix eigenvectors);
-                            batches and the adjoint take 0 only                 */
+                            the adjoint takes 0 only                            */
     double dx, dy, dz;   /* uniform cell sizes, > 0                        */
     double gamma1, pinf1;/* stiffened gas of fluid 1 (the only fluid for EULER/NS) */
     double gamma2, pinf2;/* stiffened gas of fluid 2 (FV_DIM)              */
@@ -119,8 +119,7 @@ typedef struct fv_config {
     int32_t scheme;      /* reconstruction scheme (Sec. 3.2 step 3): 0 WENO5-Z; 1 TENO6-A
                             (stencils of the reconstruction schematic, Jiang-Shu
                             indicators, adaptive cut-off; the six cells i-2..i+3
-                            of a face for both states); batches and the adjoint
-                            take 0 only                                         */
+                            of a face for both states); the adjoint takes 0 only */
     double T_ref;        /* reference temperature of the law, > 0 when visc_law != 0 */
     double sutherland;   /* Sutherland's constant C, >= 0                  */
     double gas_R;        /* specific gas constant in T = p / (rho R); 0 selects 1 */
@@ -132,7 +131,7 @@ typedef struct fv_config {
     int32_t thinc;       /* FV_DIM: 1 replaces the volume fraction and partial densities of
                             the face states of interface cells by the THINC profile
                             (Sec. 3.2; eps 1e-4, beta 1; profile centre from the cell
-                            average); 0 off.  Not in batches                    */
+                            average); 0 off                                     */
 } fv_config;
 
 /* Result of check_state. */
@@ -290,8 +289,11 @@ int workspace_time(const fv_config* cfg, const void* ws, double* t, void* stream
  *
  * Each member is one problem: its fv_config, its state U and its workspace ws
  * (workspace_bytes(cfg), exactly as for advance).  Members may differ in grid,
- * model, precision, boundary conditions and parameters.  Every RK stage of a
- * batched step is one launch per (model, precision, limiter) group, whose
+ * model, precision, boundary conditions, parameters and options (reconstruction
+ * variables and scheme, THINC, viscosity law; not visc_order 6, which needs its
+ * separate passes).  Every RK stage of a batched step is one launch per group of
+ * members sharing (model, precision, limiter setting, reconstruction variables and
+ * scheme, viscosity law or THINC on/off), at most 16 groups per batch, whose
  * workgroups are spread over the group's members through a device table, so
  * small problems fill the GPU together.  Time stepping is in CFL mode: each
  * member keeps its own dt, recomputed on the device from its own state (the
@@ -317,7 +319,8 @@ int batch_destroy(fv_batch* b);
  * now: their first dt is computed from U and their simulated time set to 0.
  * The table upload is stream-ordered: work enqueued earlier still runs on the
  * previous membership.  Captured graphs stay valid (they read the membership
- * from the table). */
+ * from the table).  FV_EUNSUPPORTED for a member with visc_order 6; FV_EINVAL when
+ * the members form more than 16 groups. */
 int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, void* const* ws, const int32_t* fresh,
               void* stream);
 
@@ -330,7 +333,7 @@ int batch_step(fv_batch* b, int32_t nsteps, void* stream);
  * the membership from the device table, and their grids are the groups'
  * workgroup counts rounded up to a multiple of an eighth of their power-of-two
  * floor (spare workgroups return at once), so one captured graph serves every
- * membership with the same (model, precision, limiter) groups and rounded grids:
+ * membership with the same groups and rounded grids:
  * graphs are cached per batch under that key, nsteps and the stream (at most 16,
  * least recently used dropped) and captured on a miss.  stream must not be the
  * default (NULL) stream; the graph runs on the stream it was captured on.  When

@@ -787,14 +787,17 @@ const char* last_error(void) { return g_err; }
 
 namespace {
 
-constexpr int MAX_GROUPS = 12;   // 3 models x 2 precisions x 2 limiter settings
+// group of a member: model x precision x limiter setting x reconstruction family x
+// variant (a viscosity law for NS, THINC for the five-equation model)
+constexpr int MAX_GROUP_IDS = 3 * 2 * 2 * 4 * 2;
+constexpr int MAX_GROUPS = 16;  // groups present in one batch (table regions)
 constexpr size_t TAB_ALIGN = 256;
 constexpr int MAX_GRAPHS = 16;   // cached step graphs per batch
 
 size_t align_up(size_t v) { return (v + TAB_ALIGN - 1) & ~(TAB_ALIGN - 1); }
 
 struct BatchGroup {
-    int gid, model, dtype, pos, count, nblocks;
+    int gid, model, dtype, pos, rec, variant, count, nblocks;
     size_t hdr_off, first_off, args_off[3];  // byte offsets in the device table
     // a group of one member runs the single-problem stage kernel with these arguments
     // (the same body: the same results, without the table indirection)
@@ -897,10 +900,10 @@ int batch_launch_steps(fv_batch* b, int nsteps, hipStream_t st, bool bucketed)
                 const int nb = bucketed ? grid_bucket(g.nblocks) : g.nblocks;
                 hipError_t e =
                     g.dtype == FV_F64
-                        ? fv::launch_batch_stage<double>(g.model, g.pos != 0,
+                        ? fv::launch_batch_stage<double>(g.model, g.rec, g.pos != 0, g.variant,
                                                          reinterpret_cast<const fv::StageArgs<double>*>(b->table + g.args_off[s]),
                                                          first, count, nb, st)
-                        : fv::launch_batch_stage<float>(g.model, g.pos != 0,
+                        : fv::launch_batch_stage<float>(g.model, g.rec, g.pos != 0, g.variant,
                                                         reinterpret_cast<const fv::StageArgs<float>*>(b->table + g.args_off[s]),
                                                         first, count, nb, st);
                 if (e != hipSuccess) return hip_fail(e, "batch stage launch");
@@ -985,31 +988,38 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
         if (r) return fail(r, "member %d: %s", i, last_error());
         if ((r = check_ptr(U[i], "U")) || (r = check_ptr(ws[i], "ws"))) return fail(r, "member %d: %s", i, last_error());
         if (!(cfgs[i].cfl > 0)) return fail(FV_EINVAL, "member %d: cfl must be > 0", i);
-        if (cfgs[i].recon != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use primitive reconstruction", i);
-        if (cfgs[i].scheme != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use WENO5-Z reconstruction", i);
         if (visc6(&cfgs[i])) return fail(FV_EUNSUPPORTED, "member %d: batches use 4th-order viscous fluxes", i);
-        if (cfgs[i].thinc) return fail(FV_EUNSUPPORTED, "member %d: batches run without THINC", i);
-        if (cfgs[i].visc_law != 0) return fail(FV_EUNSUPPORTED, "member %d: batches use constant viscosity", i);
     }
     // groups present, in the order of their id; members keep their order inside a group
-    int gcount[MAX_GROUPS] = {0};
+    int gcount[MAX_GROUP_IDS] = {0};
     std::vector<int> gid(n);
     for (int i = 0; i < n; i++) {
-        gid[i] = cfgs[i].model * 4 + cfgs[i].dtype * 2 + (positivity_on(&cfgs[i]) ? 1 : 0);
+        const fv_config* c = &cfgs[i];
+        const int variant = (c->model == FV_NS && c->visc_law != 0) || (c->model == FV_DIM && c->thinc) ? 1 : 0;
+        gid[i] = (((c->model * 2 + c->dtype) * 2 + (positivity_on(c) ? 1 : 0)) * 4 + c->recon + 2 * c->scheme) * 2 +
+                 variant;
         gcount[gid[i]]++;
     }
+    int present = 0;
+    for (int g = 0; g < MAX_GROUP_IDS; g++) present += gcount[g] ? 1 : 0;
+    if (present > MAX_GROUPS)
+        return fail(FV_EINVAL, "the members form %d groups (model, precision, limiters, reconstruction, variant); "
+                               "a batch holds at most %d",
+                    present, MAX_GROUPS);
     std::vector<BatchGroup> groups;
-    int pos_of[MAX_GROUPS];
+    int pos_of[MAX_GROUP_IDS];
     const size_t rb = region_bytes(b->capacity), ab = args_bytes(b->capacity);
-    for (int g = 0; g < MAX_GROUPS; g++) {
+    for (int g = 0; g < MAX_GROUP_IDS; g++) {
         pos_of[g] = -1;
         if (!gcount[g]) continue;
         BatchGroup ng;
         memset(&ng, 0, sizeof ng);
         ng.gid = g;
-        ng.model = g / 4;
-        ng.dtype = (g / 2) % 2;
-        ng.pos = g % 2;
+        ng.variant = g % 2;
+        ng.rec = (g / 2) % 4;
+        ng.pos = (g / 8) % 2;
+        ng.dtype = (g / 16) % 2;
+        ng.model = g / 32;
         ng.count = gcount[g];
         ng.hdr_off = groups.size() * rb;
         ng.first_off = ng.hdr_off + TAB_ALIGN;
@@ -1064,8 +1074,10 @@ int batch_set(fv_batch* b, int32_t n, const fv_config* cfgs, void* const* U, voi
     // kernel attributes before any capture
     for (const BatchGroup& g : groups) {
         hipError_t e = g.dtype == FV_F64
-                           ? fv::launch_batch_stage<double>(g.model, g.pos != 0, nullptr, nullptr, nullptr, 0, st)
-                           : fv::launch_batch_stage<float>(g.model, g.pos != 0, nullptr, nullptr, nullptr, 0, st);
+                           ? fv::launch_batch_stage<double>(g.model, g.rec, g.pos != 0, g.variant, nullptr, nullptr,
+                                                            nullptr, 0, st)
+                           : fv::launch_batch_stage<float>(g.model, g.rec, g.pos != 0, g.variant, nullptr, nullptr,
+                                                           nullptr, 0, st);
         if (e != hipSuccess) return hip_fail(e, "batch_set: kernel attributes");
     }
     hipError_t e = hipMemcpyAsync(b->table, img, end, hipMemcpyHostToDevice, st);

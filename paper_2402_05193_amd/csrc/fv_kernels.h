@@ -88,13 +88,14 @@ template <typename Real, int MODEL>
 size_t stage_lds_bytes();
 
 // Fused stage over n independent problems of one model / precision / limiter
-// setting: args[r] describes problem r, whose workgroups are first[r] ..
-// first[r+1]-1 (device arrays), n = *count (device).  nblocks >= first[n]
-// workgroups are launched (the rest return at once); nblocks 0 only prepares the
-// kernel's attributes (call before stream capture).
+// setting / reconstruction family (rec: REC_*) / variant (1: a viscosity law for NS,
+// THINC for the five-equation model): args[r] describes problem r, whose workgroups
+// are first[r] .. first[r+1]-1 (device arrays), n = *count (device).  nblocks >=
+// first[n] workgroups are launched (the rest return at once); nblocks 0 only prepares
+// the kernel's attributes (call before stream capture).
 template <typename Real>
-hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, const int* count,
-                              int nblocks, hipStream_t st);
+hipError_t launch_batch_stage(int model, int rec, bool pos, int variant, const StageArgs<Real>* args, const int* first,
+                              const int* count, int nblocks, hipStream_t st);
 
 // Sixth-order central viscous fluxes (fv_visc6.hip), three passes over the
 // state U of the viscous model:

@@ -1046,11 +1046,11 @@ __global__ void __launch_bounds__(NTH, stage_waves<Real>()) stage_kernel(const S
 }
 
 // Many independent problems in one launch: the workgroups of problem r are
-// first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision
-// and limiter setting for every problem of the launch); *count = n, read from the
-// device table so that a captured launch serves any membership (workgroups beyond
-// first[n] return at once).
-template <typename Real, int MODEL, int POS, int BX, int BY, int NTH>
+// first[r] .. first[r+1]-1; args[r] describes problem r (same model, precision,
+// limiter setting, reconstruction family and viscosity / interface variant for every
+// problem of the launch); *count = n, read from the device table so that a captured
+// launch serves any membership (workgroups beyond first[n] return at once).
+template <typename Real, int MODEL, int POS, int REC, int VMODE, int BX, int BY, int NTH>
 __global__ void __launch_bounds__(NTH, stage_waves<Real>())
     batch_stage_kernel(const StageArgs<Real>* __restrict__ args, const int* __restrict__ first,
                        const int* __restrict__ count)
@@ -1070,7 +1070,7 @@ __global__ void __launch_bounds__(NTH, stage_waves<Real>())
     // so the compiler may load its fields with scalar loads wherever it needs them
     using CArgs = const __attribute__((address_space(4))) StageArgs<Real>;
     const StageArgs<Real>* pa = (const StageArgs<Real>*)(CArgs*)(args + lo);
-    stage_body<Real, MODEL, POS, REC_WENO_PRIM, VM_CONST, BX, BY, NTH>(*pa, b - first[lo], smem_raw);
+    stage_body<Real, MODEL, POS, REC, VMODE, BX, BY, NTH>(*pa, b - first[lo], smem_raw);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1140,13 +1140,14 @@ hipError_t launch_model(const StageArgs<Real>& args, const LaunchGeom& g, hipStr
     }
 }
 
-template <typename Real, int MODEL, int POS>
+template <typename Real, int MODEL, int POS, int REC, int VMODE>
 static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* first, const int* count, int nblocks,
                                     hipStream_t st)
 {
-    using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT>;
+    using TL = Tile<Real, MODEL, TILE_BX, TILE_BY, TILE_NT, MODEL == NS && VMODE != VM_EXT && VMODE != VM_EXT_LAW,
+                    MODEL == DIM && VMODE == XM_THINC>;
     const size_t lds = TL::bytes();
-    auto* k = batch_stage_kernel<Real, MODEL, POS, TILE_BX, TILE_BY, TILE_NT>;
+    auto* k = batch_stage_kernel<Real, MODEL, POS, REC, VMODE, TILE_BX, TILE_BY, TILE_NT>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1158,25 +1159,46 @@ static hipError_t launch_batch_tile(const StageArgs<Real>* args, const int* firs
     return hipGetLastError();
 }
 
-// the batched kernels of one precision and model (instantiated with that model's
-// primitive WENO5-Z family in fv_stage_inst.hip, so that they are compiled with the same
-// code-generation options as the single-problem kernel they share their body with)
-template <typename Real, int MODEL>
-hipError_t launch_batch_model(bool pos, const StageArgs<Real>* args, const int* first, const int* count, int nblocks,
-                              hipStream_t st)
+// the batched kernels of one precision, model and reconstruction family, instantiated
+// with that family's single-problem kernels in fv_stage_inst.hip (so that they are
+// compiled with the same code-generation options as the kernels they share their body
+// with); variant: 0 constant viscosity / no THINC, 1 a viscosity law (NS) or THINC
+// (five-equation model)
+template <typename Real, int MODEL, int REC>
+hipError_t launch_batch_rec(bool pos, int variant, const StageArgs<Real>* args, const int* first, const int* count,
+                            int nblocks, hipStream_t st)
 {
-    return pos ? launch_batch_tile<Real, MODEL, 1>(args, first, count, nblocks, st)
-               : launch_batch_tile<Real, MODEL, 0>(args, first, count, nblocks, st);
+    if constexpr (MODEL != EULER) {
+        if (variant) {
+            constexpr int VM = MODEL == DIM ? XM_THINC : VM_LAW;
+            return pos ? launch_batch_tile<Real, MODEL, 1, REC, VM>(args, first, count, nblocks, st)
+                       : launch_batch_tile<Real, MODEL, 0, REC, VM>(args, first, count, nblocks, st);
+        }
+    }
+    return pos ? launch_batch_tile<Real, MODEL, 1, REC, VM_CONST>(args, first, count, nblocks, st)
+               : launch_batch_tile<Real, MODEL, 0, REC, VM_CONST>(args, first, count, nblocks, st);
+}
+
+template <typename Real, int MODEL>
+hipError_t launch_batch_model(int rec, bool pos, int variant, const StageArgs<Real>* args, const int* first,
+                              const int* count, int nblocks, hipStream_t st)
+{
+    switch (rec) {
+    case REC_WENO_CHAR: return launch_batch_rec<Real, MODEL, REC_WENO_CHAR>(pos, variant, args, first, count, nblocks, st);
+    case REC_TENO_PRIM: return launch_batch_rec<Real, MODEL, REC_TENO_PRIM>(pos, variant, args, first, count, nblocks, st);
+    case REC_TENO_CHAR: return launch_batch_rec<Real, MODEL, REC_TENO_CHAR>(pos, variant, args, first, count, nblocks, st);
+    default: return launch_batch_rec<Real, MODEL, REC_WENO_PRIM>(pos, variant, args, first, count, nblocks, st);
+    }
 }
 
 template <typename Real>
-hipError_t launch_batch_stage(int model, bool pos, const StageArgs<Real>* args, const int* first, const int* count,
-                              int nblocks, hipStream_t st)
+hipError_t launch_batch_stage(int model, int rec, bool pos, int variant, const StageArgs<Real>* args, const int* first,
+                              const int* count, int nblocks, hipStream_t st)
 {
     switch (model) {
-    case EULER: return launch_batch_model<Real, EULER>(pos, args, first, count, nblocks, st);
-    case NS: return launch_batch_model<Real, NS>(pos, args, first, count, nblocks, st);
-    default: return launch_batch_model<Real, DIM>(pos, args, first, count, nblocks, st);
+    case EULER: return launch_batch_model<Real, EULER>(rec, pos, 0, args, first, count, nblocks, st);
+    case NS: return launch_batch_model<Real, NS>(rec, pos, variant, args, first, count, nblocks, st);
+    default: return launch_batch_model<Real, DIM>(rec, pos, variant, args, first, count, nblocks, st);
     }
 }
 

@@ -9,9 +9,7 @@
 
 namespace fv {
 template hipError_t launch_rec<FV_REAL, FV_MODEL, FV_REC>(const StageArgs<FV_REAL>&, const LaunchGeom&, hipStream_t);
-#if FV_REC == 0
-// the batched kernels share the primitive WENO5-Z body
-template hipError_t launch_batch_model<FV_REAL, FV_MODEL>(bool, const StageArgs<FV_REAL>*, const int*, const int*, int,
-                                                          hipStream_t);
-#endif
+// the batched kernels of the same family share its body and compile options
+template hipError_t launch_batch_rec<FV_REAL, FV_MODEL, FV_REC>(bool, int, const StageArgs<FV_REAL>*, const int*,
+                                                                const int*, int, hipStream_t);
 }  // namespace fv

@@ -6,6 +6,7 @@ problem the same arithmetic); graph replays equal the eager batched steps
 bitwise; FP64 members follow the FP64 oracle within the multi-step bar 1e-10;
 FP32 members state their error against the FP64 oracle.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -53,6 +54,33 @@ def grouped_jobs(steps=8):
             job(3, S.F32, SMALL_GRIDS[3], steps, two_phase=True),
             tgv_job(4, steps=steps),
             job(5, S.F64, SMALL_GRIDS[2], steps, two_phase=False)]
+
+
+def option_jobs(steps=6):
+    """Members with the reconstruction, interface and viscosity options, two per group
+    (so that batched launches, not the single-problem path, run them) plus one alone:
+    characteristic WENO5-Z (Euler FP64), TENO6-A (five-equation FP32), characteristic
+    TENO6-A with THINC (five-equation FP64), THINC (five-equation FP32), Sutherland's
+    viscosity law (NS FP64) and TENO6-A alone (NS FP64)."""
+    out = []
+
+    def add(j, **over):
+        j.cfg = dataclasses.replace(j.cfg, **over)
+        j.index = len(out)
+        out.append(j)
+
+    for g in SMALL_GRIDS[:2]:
+        add(job(0, S.F64, g, steps, two_phase=False), recon=1)
+    for g in SMALL_GRIDS[2:]:
+        add(job(0, S.F32, g, steps, two_phase=True), scheme=1)
+    for g in SMALL_GRIDS[:2]:
+        add(job(0, S.F64, g, steps, two_phase=True), recon=1, scheme=1, thinc=1)
+    for g in SMALL_GRIDS[1:3]:
+        add(job(0, S.F32, g, steps, two_phase=True), thinc=1)
+    for n in (16, 12):
+        add(tgv_job(0, n=n, steps=steps), visc_law=2, T_ref=1.0, sutherland=0.4, gas_R=1.0)
+    add(tgv_job(0, n=12, steps=steps), scheme=1)
+    return out
 
 
 def allocate(j):
@@ -116,6 +144,35 @@ def test_batch_members_join_and_leave_bitwise_alone():
         t = S.advance(j.cfg, U, j.steps, 0.0, ws, t=0.0)
         assert S.workspace_time(j.cfg, j.ws) == t
     b.close()
+
+
+def test_batch_members_with_options_bitwise_alone():
+    """Members with the f3/f4 options (reconstruction family, THINC, a viscosity law)
+    in one batch, stepped eagerly and through graph replays: every member ends bitwise
+    equal to its solo run."""
+    eager, graph = option_jobs(), option_jobs()
+    for j in eager + graph:
+        allocate(j)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        be, bg = S.Batch(16), S.Batch(16)
+        be.set([(j.cfg, j.U, j.ws) for j in eager], fresh=[True] * len(eager), stream=stream)
+        bg.set([(j.cfg, j.U, j.ws) for j in graph], fresh=[True] * len(graph), stream=stream)
+        steps = eager[0].steps
+        be.step(steps, stream=stream)
+        for _ in range(steps):
+            bg.step_graph(1, stream=stream)
+        stream.synchronize()
+        for je, jg in zip(eager, graph):
+            what = (f"member {je.index} (model {je.cfg.model}, dtype {je.cfg.dtype}, recon {je.cfg.recon}, "
+                    f"scheme {je.cfg.scheme}, thinc {je.cfg.thinc}, visc_law {je.cfg.visc_law})")
+            print(f"[serving] {what}", flush=True)
+            ref = alone(je, steps)
+            assert torch.isfinite(ref).all()
+            assert_bitwise(je.U, ref, what + " eager")
+            assert_bitwise(jg.U, ref, what + " graph")
+        be.close()
+        bg.close()
 
 
 def test_batch_graph_replays_equal_eager_steps():
