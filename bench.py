@@ -238,7 +238,7 @@ def run_oracle_baseline(n: int, model: int) -> dict:
 
 def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: int = 2402,
                 low_rate: float = 20.0, low_n: int = 80, fill: int | None = 768, use_graph: bool = True,
-                policy: str = "srpt", backlog: int | None = 8) -> dict:
+                policy: str = "srpt", backlog: int | None = 8, protect_oldest: bool = False) -> dict:
     """Serving benchmark: a seeded Poisson stream of independent 3-D Riemann problems
     (single- and two-phase, grids 64^3 .. 256x128x128, 50 RK3 steps each, FP32, CFL 0.5),
     served by continuous batching (graph replay; admission by memory and, with fill, by
@@ -250,7 +250,7 @@ def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: 
     from paper_2402_05193_amd import workloads as WL
 
     srv = SV.Server(pool_bytes=int(pool_gib * (1 << 30)), max_batch=max_batch, use_graph=use_graph,
-                    fill_workgroups=fill, policy=policy, backlog=backlog)
+                    fill_workgroups=fill, policy=policy, backlog=backlog, protect_oldest=protect_oldest)
     # warm-up: every kernel variant once on both paths (tiny grids)
     warm = lambda: [SV.job_from_request(WL.riemann_request(i, seed + 1, grids=((16, 16, 16),), steps=2), 0.0)
                     for i in range(6)]
@@ -276,7 +276,7 @@ def run_serving(n_req: int, rate: float, max_batch: int, pool_gib: float, seed: 
     out = {"workload": f"Poisson stream of planar 3-D Riemann problems (Euler / five-equation air-helium, "
                        f"grids {list(WL.SERVING_GRIDS)}), 50 TVD-RK3 steps each at CFL 0.5, FP32, limiters on",
            "max_batch": max_batch, "pool_gib": pool_gib, "fill_workgroups": fill, "policy": policy,
-           "backlog": backlog,
+           "backlog": backlog, "protect_oldest": protect_oldest,
            "offered": main,
            "graphs_cached": srv.batch.graph_count()}
     if low is not None:
@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--serve-policy", choices=["srpt", "fcfs"], default="srpt",
                     help="srpt: each step advances the resident requests with the least remaining work that fit "
                          "the fill budget; fcfs: requests join in arrival order and stay until done")
+    ap.add_argument("--serve-protect-oldest", action="store_true",
+                    help="srpt: step the oldest resident request in every step (shorter tail, longer median)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-batch", type=int, default=32)
     ap.add_argument("--serve-pool-gib", type=float, default=12.0)
@@ -414,7 +416,8 @@ def main():
         res = run_serving(args.serve_requests, args.serve_rate, args.serve_max_batch, args.serve_pool_gib,
                           low_rate=args.serve_low_rate, low_n=args.serve_low_requests,
                           fill=args.serve_fill if args.serve_fill > 0 else None, use_graph=not args.serve_eager,
-                          policy=args.serve_policy, backlog=args.serve_backlog if args.serve_backlog > 0 else None)
+                          policy=args.serve_policy, backlog=args.serve_backlog if args.serve_backlog > 0 else None,
+                          protect_oldest=args.serve_protect_oldest)
         print(json.dumps({"serving": res}), flush=True)
         return
     model = {"ns": S.NS, "euler": S.EULER, "dim": S.DIM}[args.model]
@@ -586,7 +589,8 @@ def main():
                                      low_n=args.serve_low_requests,
                                      fill=args.serve_fill if args.serve_fill > 0 else None,
                                      use_graph=not args.serve_eager, policy=args.serve_policy,
-                                     backlog=args.serve_backlog if args.serve_backlog > 0 else None)
+                                     backlog=args.serve_backlog if args.serve_backlog > 0 else None,
+                                     protect_oldest=args.serve_protect_oldest)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint_bench()
         print(f"[bench] adjoint: {json.dumps(out['adjoint'])}", flush=True)

@@ -144,7 +144,7 @@ class Server:
 
     def __init__(self, pool_bytes: int = 12 << 30, max_batch: int = 32, device="cuda", use_graph: bool = True,
                  max_inflight: int = 2, fill_workgroups: int | None = None, policy: str = "fcfs",
-                 backlog: int | None = None):
+                 backlog: int | None = None, protect_oldest: bool = False):
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)  # default priority
         self.arena = torch.empty(int(pool_bytes) // ALIGN * ALIGN, dtype=torch.uint8, device=self.device)
@@ -169,6 +169,12 @@ class Server:
         # lifted and every resident request (up to max_batch) steps together, for
         # throughput; None keeps the budget at any load
         self.backlog = backlog
+        # srpt: the resident request admitted first steps in every step even when the
+        # budget is spent on smaller ones, so that a stream of small requests cannot hold
+        # a large one back indefinitely.  Measured on the FP32 Riemann stream at 20
+        # requests/s (600 requests): p99 0.22 against 0.26 s, p50 0.042 against 0.037 s
+        # (one at a time: 0.21 and 0.041 s); off by default
+        self.protect_oldest = protect_oldest
 
     # ---------------------------------------------------------------- memory
     @staticmethod
@@ -348,6 +354,12 @@ class Server:
                         break
                     chosen.append(j)
                     wg += j.workgroups
+                if self.protect_oldest:
+                    oldest = min(resident, key=lambda x: (x.admitted, x.index))
+                    if oldest not in chosen:
+                        if len(chosen) >= self.max_batch:
+                            chosen.pop()
+                        chosen.append(oldest)
                 if [j.index for j in chosen] != [j.index for j in members] or any(j.index in fresh for j in chosen):
                     members = chosen
                     self.batch.set([(j.cfg, j.U, j.ws) for j in members],
