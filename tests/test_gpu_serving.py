@@ -291,7 +291,7 @@ def test_batched_fp64_members_follow_the_oracle():
 
 
 @pytest.mark.parametrize("use_graph,fill,policy", [(False, None, "fcfs"), (True, None, "fcfs"), (True, 40, "fcfs"),
-                                                   (True, 40, "srpt"), (False, None, "srpt")])
+                                                   (True, 40, "srpt"), (False, None, "srpt"), (True, 40, "srpt-oldest")])
 def test_server_results_same_alone_and_in_the_mix(use_graph, fill, policy):
     """Continuous batching with admission by memory (and by GPU fill), in arrival
     order or least remaining work first (members paused between steps): an arena
@@ -302,7 +302,8 @@ def test_server_results_same_alone_and_in_the_mix(use_graph, fill, policy):
     for k, j in enumerate(jobs):
         j.arrival = 0.002 * k
     biggest = max(SV.Server.job_bytes(j.cfg) for j in jobs)
-    srv = SV.Server(pool_bytes=3 * biggest, max_batch=4, use_graph=use_graph, fill_workgroups=fill, policy=policy)
+    srv = SV.Server(pool_bytes=3 * biggest, max_batch=4, use_graph=use_graph, fill_workgroups=fill,
+                    policy=policy.split("-")[0], protect_oldest=policy.endswith("oldest"))
     st = srv.run_batched(jobs, keep_results=True)
     assert st.n == len(jobs) and st.max_batch_seen <= 4
     assert all(j.finish >= j.arrival for j in jobs)
