@@ -37,6 +37,9 @@
  *    Jiang-Shu indicators, tau_6 = |beta_6 - (beta_0 + 4 beta_1 + beta_2)/6|,
  *    C = 1, q = 6, the adaptive cut-off with a1 = 10.5, a2 = 3.5, C_r = 0.17,
  *    xi = 1e-3, and the sixth-order linear weights (see orc_teno6a_parts).
+ *    Parity unpinned for these constants: the cited scheme is not at hand, and
+ *    the property tests fix the structure (indicators, cut-off limits,
+ *    exactness, order of accuracy), not the values.
  *
  * Operand order in a few places is chosen so that the result of a mirrored
  * input is the exact mirror image (e.g. the s* numerator is formed as
