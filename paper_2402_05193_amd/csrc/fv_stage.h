@@ -704,7 +704,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
 
         if (xy) {
             Real* slot = ACC + (s & 1) * NC * NCELL + tid;  // partial sums of cell s (ACC_LDS)
+            // FP64: waves with more work than the others in a phase (the remainder of a task
+            // list) take a higher issue priority on their SIMD until the phase's barrier, over
+            // the co-resident workgroup's waves, so that the workgroup reaches the barrier
+            // sooner: the reconstruction phases' remainder waves priority 1, the face phases'
+            // remainder wave priority 2.  NS 256^3 2.260 -> 2.18 ms per stage, five-equation
+            // 256x128x128 0.949 -> 0.914 ms, Euler equal; FP32 (three workgroups per CU)
+            // measured 0.4-2 % slower with it and keeps the default priority.
+            constexpr int P1_ITEMS = CHARV ? TL::NFX : (TENO ? NC * TL::NFX : NC * (BX + 2) * BY);
+            constexpr int P4_ITEMS = CHARV ? TL::NFY : (TENO ? NC * TL::NFY : NC * BX * (BY + 2));
+            const bool prio_p1 = sizeof(Real) == 8 && (rt >> 6) < ((P1_ITEMS % NT) + 63) / 64;
+            const bool prio_p4 = sizeof(Real) == 8 && (rt >> 6) < ((P4_ITEMS % NT) + 63) / 64;
             // ---- P1: x reconstructions (cells -1 .. BX of each row) [+ d/dy on the x region]
+            if (prio_p1) __builtin_amdgcn_s_setprio(1);
             Real* FL = FB;
             Real* FR = FB + NC * TL::NFX;
             if constexpr (CHARV) {
@@ -752,14 +764,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     DT[it] = dcell(wp(V + c, i, j - 2), wp(V + c, i, j - 1), wp(V + c, i, j + 1), wp(V + c, i, j + 2), i12);
                 }
             }
+            if (prio_p1) __builtin_amdgcn_s_setprio(0);
             __syncthreads();
             // ---- P2: x faces f = 0 .. BX (between cells f-1 and f)
-            // The wave holding rt = 0 also runs the remainder round of the x and y face
-            // lists while the workgroup's other waves wait at the next barrier; in FP64 it
-            // takes a higher issue priority on its SIMD during the face phases (over the
-            // co-resident workgroup's wave): NS 256^3 2.260 -> 2.245 ms per stage,
-            // five-equation 256x128x128 0.949 -> 0.932 ms; FP32 (three workgroups per CU)
-            // measured 0.4 % slower with it and keeps the default priority.
+            // the wave holding rt = 0 also runs the remainder round of the x and y face lists
             const bool prio_tail = sizeof(Real) == 8 && (rt >> 6) == 0;  // wave-uniform
             if (prio_tail) __builtin_amdgcn_s_setprio(2);
             for (int t = rt; t < TL::NFX; t += NT) {
@@ -846,6 +854,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
             __syncthreads();
             // ---- P4: y reconstructions (rows -1 .. BY of each column) [+ d/dx on the y region]
+            if (prio_p4) __builtin_amdgcn_s_setprio(1);
             Real* GL = FB;
             Real* GR = FB + NC * TL::NFY;
             if constexpr (CHARV) {
@@ -893,6 +902,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     DT[it] = dcell(wp(f, i - 2, j), wp(f, i - 1, j), wp(f, i + 1, j), wp(f, i + 2, j), i12);
                 }
             }
+            if (prio_p4) __builtin_amdgcn_s_setprio(0);
             __syncthreads();
             // ---- P5: y faces f = 0 .. BY (between rows f-1 and f)
             if (prio_tail) __builtin_amdgcn_s_setprio(2);
