@@ -204,6 +204,25 @@ __device__ __forceinline__ void prim_to_cons(const Material<Real>& mat, const Re
 // Weights alpha_k = d_k (1 + tau / (beta_k + eps)) with tau = |beta0 - beta2|
 // (WENO-Z, exponent 1).  The 1/(beta_k + eps) and the factors
 // g_k = 1 + tau/(beta_k + eps) are computed once for both sides.
+// WENO-Z weights (q = 1) in FP32 for data of any magnitude: g_k = 1 + tau / e_k
+// (e_k = beta_k + eps) overflows once tau exceeds ~1e8 with eps = 1e-30 (a jump
+// of ~2e4 in the reconstructed variable, e.g. a pressure jump in pascals).  The
+// weights divided by the largest one, s_k = g_k / max g = A + C e_min / e_k with
+// A = e_min / (e_min + tau) and C = tau / (e_min + tau) = 1 - A, normalise to the
+// same nonlinear weights, stay in [0, 1] and keep s = 1 for the smoothest
+// candidate when A underflows (tau / e_min beyond the FP32 range).  FP64
+// (eps = 1e-40) keeps the plain form.
+__device__ __forceinline__ void weno_z_scaled(float tau, float e0, float e1, float e2, float& s0, float& s1,
+                                              float& s2)
+{
+    const float em = fminf(fminf(e0, e1), e2);
+    const float inv = rcp(em + tau);
+    const float A = em * inv, C = tau * inv;
+    s0 = fmaf(C, em * rcp(e0), A);
+    s1 = fmaf(C, em * rcp(e1), A);
+    s2 = fmaf(C, em * rcp(e2), A);
+}
+
 template <typename Real>
 __device__ __forceinline__ void weno5z_pair(Real a, Real b, Real c, Real d, Real e, Real eps, Real& vm,
                                             Real& vp)
@@ -220,23 +239,21 @@ __device__ __forceinline__ void weno5z_pair(Real a, Real b, Real c, Real d, Real
     const Real b2 = k13 * t2 * t2 + q * s2 * s2;
     const Real tau = fabs(b0 - b2);
     const Real e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
-    Real r0, r1, r2;
+    Real g0, g1, g2;
     if constexpr (sizeof(Real) == 8) {
         // one reciprocal for the three indicators: 1/e_k from 1/(e0 e1 e2)
         const Real p01 = e0 * e1;
         const Real R = rcp(p01 * e2);
         const Real t = e2 * R;
-        r2 = p01 * R;
-        r0 = e1 * t;
-        r1 = e0 * t;
+        const Real r2 = p01 * R;
+        const Real r0 = e1 * t;
+        const Real r1 = e0 * t;
+        g0 = fma(tau, r0, Real(1));
+        g1 = fma(tau, r1, Real(1));
+        g2 = fma(tau, r2, Real(1));
     } else {
-        r0 = rcp(e0);
-        r1 = rcp(e1);
-        r2 = rcp(e2);
+        weno_z_scaled(tau, e0, e1, e2, g0, g1, g2);
     }
-    const Real g0 = fma(tau, r0, Real(1));
-    const Real g1 = fma(tau, r1, Real(1));
-    const Real g2 = fma(tau, r2, Real(1));
     // candidate values (times 6)
     const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
     const Real p1 = -b + Real(5) * c + Real(2) * d;
@@ -278,22 +295,22 @@ __device__ __forceinline__ Real weno5z_one(Real a, Real b, Real c, Real d, Real 
     const Real b2 = k13 * t2 * t2 + q * s2 * s2;
     const Real tau = fabs(b0 - b2);
     const Real e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
-    Real r0, r1, r2;
+    Real g0, g1, g2;
     if constexpr (sizeof(Real) == 8) {
         const Real p01 = e0 * e1;
         const Real R = rcp(p01 * e2);
         const Real t = e2 * R;
-        r2 = p01 * R;
-        r0 = e1 * t;
-        r1 = e0 * t;
+        const Real r2 = p01 * R;
+        const Real r0 = e1 * t;
+        const Real r1 = e0 * t;
+        g0 = fma(tau, r0, Real(1));
+        g1 = fma(tau, r1, Real(1));
+        g2 = fma(tau, r2, Real(1));
     } else {
-        r0 = rcp(e0);
-        r1 = rcp(e1);
-        r2 = rcp(e2);
+        weno_z_scaled(tau, e0, e1, e2, g0, g1, g2);
     }
-    const Real g0 = fma(tau, r0, Real(1));
-    const Real m1 = Real(6) * fma(tau, r1, Real(1));
-    const Real m2 = Real(3) * fma(tau, r2, Real(1));
+    const Real m1 = Real(6) * g1;
+    const Real m2 = Real(3) * g2;
     const Real p0 = Real(2) * a - Real(7) * b + Real(11) * c;
     const Real p1 = -b + Real(5) * c + Real(2) * d;
     const Real p2 = Real(2) * c + Real(5) * d - e;
@@ -341,7 +358,9 @@ __device__ __forceinline__ Real teno6a_cutoff(Real a, Real b, Real c, Real d, Re
 //  * stencil k is dropped when gamma_k / sum gamma < C_T, gamma_k =
 //    (1 + tau_6 / (beta_k + eps))^6; evaluated as s_k^6 < C_T sum s^6 with
 //    s_k = gamma_k^(1/6) / max gamma^(1/6) = A + A tau_6 / (beta_k + eps),
-//    A = e_min / (e_min + tau_6), which stays finite where gamma overflows.
+//    A = e_min / (e_min + tau_6), which stays finite where gamma overflows
+//    (FP32: A + C e_min / e_k with C = tau_6 / (e_min + tau_6), the same value,
+//    which keeps s = 1 for the smoothest candidate where A underflows).
 //  * kept stencils combine with the linear weights (1, 9, 6, 4) / 20.
 template <typename Real>
 __device__ __forceinline__ Real teno6a_one(Real a, Real b, Real c, Real d, Real e, Real f, Real eps, Real ct)
@@ -381,13 +400,25 @@ __device__ __forceinline__ Real teno6a_one(Real a, Real b, Real c, Real d, Real 
         r3 = rcp(e3);
     }
     const Real em = fmin(fmin(e0, e1), fmin(e2, e3));
-    const Real An = em * rcp(em + tau), Bn = An * tau;
     auto pow6 = [](Real x) {
         const Real x2 = x * x;
         return x2 * x2 * x2;
     };
-    const Real g0 = pow6(fma(Bn, r0, An)), g1 = pow6(fma(Bn, r1, An));
-    const Real g2 = pow6(fma(Bn, r2, An)), g3 = pow6(fma(Bn, r3, An));
+    Real g0, g1, g2, g3;
+    if constexpr (sizeof(Real) == 8) {
+        const Real An = em * rcp(em + tau), Bn = An * tau;
+        g0 = pow6(fma(Bn, r0, An));
+        g1 = pow6(fma(Bn, r1, An));
+        g2 = pow6(fma(Bn, r2, An));
+        g3 = pow6(fma(Bn, r3, An));
+    } else {
+        const Real inv = rcp(em + tau);
+        const Real An = em * inv, Cn = tau * inv;
+        g0 = pow6(fma(Cn, em * r0, An));
+        g1 = pow6(fma(Cn, em * r1, An));
+        g2 = pow6(fma(Cn, em * r2, An));
+        g3 = pow6(fma(Cn, em * r3, An));
+    }
     const Real thr = ct * (g0 + g1 + g2 + g3);
     const Real w0 = g0 >= thr ? Real(1) : Real(0), w1 = g1 >= thr ? Real(9) : Real(0);
     const Real w2 = g2 >= thr ? Real(6) : Real(0), w3 = g3 >= thr ? Real(4) : Real(0);
