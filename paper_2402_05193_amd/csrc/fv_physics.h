@@ -210,7 +210,9 @@ __device__ __forceinline__ void prim_to_cons(const Material<Real>& mat, const Re
 // weights divided by the largest one, s_k = g_k / max g = A + C e_min / e_k with
 // A = e_min / (e_min + tau) and C = tau / (e_min + tau) = 1 - A, normalise to the
 // same nonlinear weights, stay in [0, 1] and keep s = 1 for the smoothest
-// candidate when A underflows (tau / e_min beyond the FP32 range).  FP64
+// candidate when A underflows (tau / e_min beyond the FP32 range).  Weights of
+// order one also keep the weighted sums of small-valued fields out of the
+// denormal range, which weights scaled by e_min (>= eps) do not.  FP64
 // (eps = 1e-40) keeps the plain form.
 __device__ __forceinline__ void weno_z_scaled(float tau, float e0, float e1, float e2, float& s0, float& s1,
                                               float& s2)
