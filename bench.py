@@ -83,11 +83,12 @@ def _elf_sections(elf: bytes):
     return [(elf[names + s[0]:elf.index(b"\0", names + s[0])].decode(), s) for s in secs]
 
 
-def stage_kernel_hash() -> str:
-    """Fingerprint of the benchmarked stage kernel: a hash of its gfx950 machine code
-    and kernel descriptor (register and LDS allocation), read from the code objects
-    bundled in the built library.  Unrelated changes to the sources (other template
-    instantiations) leave it unchanged; any change to this kernel changes it."""
+def stage_kernel_hash(symbol: str = STAGE_KERNEL_SYMBOL) -> str:
+    """Fingerprint of the benchmarked stage kernel (or of another kernel of the library,
+    by its mangled name): a hash of its gfx950 machine code and kernel descriptor
+    (register and LDS allocation), read from the code objects bundled in the built
+    library.  Unrelated changes to the sources (other template instantiations) leave it
+    unchanged; any change to this kernel changes it."""
     from paper_2402_05193_amd import solver as S
     with open(S.LIB_PATH, "rb") as fh:
         so = fh.read()
@@ -114,7 +115,7 @@ def stage_kernel_hash() -> str:
                 for k in range(sym[5] // 24):
                     name_off, info, _, shndx, value, ssize = struct.unpack_from("<IBBHQQ", co, sym[4] + k * 24)
                     name = co[strtab + name_off:co.index(b"\0", strtab + name_off)].decode()
-                    if name in (STAGE_KERNEL_SYMBOL, STAGE_KERNEL_SYMBOL + ".kd"):
+                    if name in (symbol, symbol + ".kd"):
                         sec = secs[shndx][1]
                         start = sec[4] + value - sec[3]
                         body = bytearray(co[start:start + ssize])
@@ -124,7 +125,7 @@ def stage_kernel_hash() -> str:
                         found += 1
         pos = fat.find(magic, pos + len(magic))
     if found != 2:
-        raise RuntimeError(f"stage kernel {STAGE_KERNEL_SYMBOL} not found in the built library")
+        raise RuntimeError(f"kernel {symbol} not found in the built library")
     return h.hexdigest()[:16]
 
 

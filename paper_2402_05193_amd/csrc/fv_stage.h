@@ -330,6 +330,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
         // other loads are issued (its conversion waits for it and would hold them back),
         // else at the start of the step (measured faster so); converted after those loads
         constexpr bool LATE_OWN = MODEL != DIM && sizeof(Real) == 8;
+        // five-equation model (no viscous fluxes, so plane s+2 is not read before the next
+        // step): loaded after the z work and converted at the end of the step, so that
+        // neither the loaded nor the converted values are live during the z faces (the
+        // limited FP64 kernel's VGPR spills 106 -> 93, and its loads no longer wait at the
+        // end of the previous step to be spilled: 0.914 -> 0.888 ms per stage at
+        // 256x128x128, THINC 1.357 -> 1.316, FP32 1-2 % faster); the FP64 TENO6-A and
+        // characteristic kernels measured 0.2-1 % slower so and keep the early load
+        constexpr bool OWN_AFTER_Z = MODEL == DIM && (sizeof(Real) == 4 || REC == REC_WENO_PRIM);
         Real raw[NC];
         int rrefl = 0;
         auto load_own = [&]() {
@@ -344,7 +352,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             cons_to_prim<Real, MODEL>(mat, raw, win[NWIN - 1]);
             if constexpr (THINC) psw[NWIN - 1] = thinc_psi(win[NWIN - 1][6]);
         };
-        if constexpr (!LATE_OWN) load_own();
+        if constexpr (!LATE_OWN && !OWN_AFTER_Z) load_own();
         const bool xy = (s >= z0) && (s < z1);
         // THINC also stages plane z1 (the cell above the last z face of the chunk)
         const bool need_plane = xy || (VISC && s >= z0 - 2) || (THINC && s >= z0 - 1 && s <= z1);
@@ -476,7 +484,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                     ring_ap = a.Uk[6 * a.ncell + kp * plane + col];
                 }
             }
-            convert_own();
+            if constexpr (!OWN_AFTER_Z) convert_own();
             const bool prev_xy = (s - 1 >= z0) && (s - 1 < z1);
             if (!prev_xy) __syncthreads();
             // ---- P0: stage plane s in LDS (own cell from the window, halo ring from memory)
@@ -559,7 +567,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Anew[0] = (wp(NC, tx + 1, ty) - wp(NC, tx - 1, ty)) * (Real(0.5) * idx);
                 Anew[1] = (wp(NC, tx, ty + 1) - wp(NC, tx, ty - 1)) * (Real(0.5) * idy);
             }
-        } else {
+        } else if constexpr (!OWN_AFTER_Z) {
             convert_own();
         }
 
@@ -702,6 +710,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             }
         }
 
+        if constexpr (OWN_AFTER_Z) load_own();
         if (xy) {
             Real* slot = ACC + (s & 1) * NC * NCELL + tid;  // partial sums of cell s (ACC_LDS)
             // FP64: waves with more work than the others in a phase (the remainder of a task
@@ -1023,6 +1032,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
                 Ag[1][c] = Anew[c];
             }
         }
+        if constexpr (OWN_AFTER_Z) convert_own();
 #pragma unroll
         for (int q = 0; q < NWIN - 1; q++)
 #pragma unroll
