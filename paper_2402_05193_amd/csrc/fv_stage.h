@@ -326,18 +326,22 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
     }
 
     for (int s = s_begin; s <= z1 + 1; s++) {
-        // own column, plane s+2: for the FP64 single-phase kernels loaded after the step's
-        // other loads are issued (its conversion waits for it and would hold them back),
-        // else at the start of the step (measured faster so); converted after those loads
-        constexpr bool LATE_OWN = MODEL != DIM && sizeof(Real) == 8;
-        // five-equation model (no viscous fluxes, so plane s+2 is not read before the next
-        // step): loaded after the z work and converted at the end of the step, so that
-        // neither the loaded nor the converted values are live during the z faces (the
-        // limited FP64 kernel's VGPR spills 106 -> 93, and its loads no longer wait at the
-        // end of the previous step to be spilled: 0.914 -> 0.888 ms per stage at
-        // 256x128x128, THINC 1.357 -> 1.316, FP32 1-2 % faster); the FP64 TENO6-A and
-        // characteristic kernels measured 0.2-1 % slower so and keep the early load
-        constexpr bool OWN_AFTER_Z = MODEL == DIM && (sizeof(Real) == 4 || REC == REC_WENO_PRIM);
+        // own column, plane s+2.  Without viscous fluxes it is not read before the next
+        // step: the five-equation and Euler kernels load it after the z work and convert it
+        // at the end of the step (OWN_AFTER_Z), so that neither the loaded nor the converted
+        // values are live during the z faces and the load's latency is covered by the x/y
+        // phases (five-equation FP64: VGPR spills 106 -> 93, and its loads no longer wait at
+        // the end of the previous step to be spilled: 0.914 -> 0.888 ms per stage at
+        // 256x128x128, THINC 1.357 -> 1.316, FP32 1-2 % faster; Euler 256^3 1.673 -> 1.649
+        // ms, FP32 0.953 -> 0.934, characteristic 2.274 -> 2.246).  The five-equation FP64
+        // TENO6-A and characteristic kernels and the Euler TENO6-A kernels measured 0.2-2 %
+        // slower so and keep an early load.  An early load is issued after the step's other
+        // loads for the remaining FP64 single-phase kernels (LATE_OWN: its conversion waits
+        // for it and would hold them back), else at the start of the step (measured faster
+        // so); either way it is converted once those loads are issued.
+        constexpr bool OWN_AFTER_Z =
+            (MODEL == DIM && (sizeof(Real) == 4 || REC == REC_WENO_PRIM)) || (MODEL == EULER && !TENO);
+        constexpr bool LATE_OWN = MODEL != DIM && sizeof(Real) == 8 && !OWN_AFTER_Z;
         Real raw[NC];
         int rrefl = 0;
         auto load_own = [&]() {
