@@ -384,9 +384,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // threads with PSI_CARRY) and the second ring's arms; a halo thread evaluates
             // it only there
             bool hpsi_needed = true;
-            const bool has_halo = tid < TL::NHALO;
+            // FP64 five-equation WENO5-Z kernels: the halo index passes through an empty asm
+            // here, so that the halo loads are issued in this step; the compiler otherwise
+            // moved them to the end of the previous step, where their values, live across
+            // the loop's back edge, were spilled as they arrived (each spill waiting for its
+            // load).  Spills 93 -> 76 VGPRs, 0.889 -> 0.830 ms per stage at 256x128x128,
+            // THINC 1.314 -> 1.295 ms; the other kernels measured equal or 0.3-1.2 % slower
+            // with it.
+            constexpr bool HALO_IN_STEP = MODEL == DIM && REC == REC_WENO_PRIM && sizeof(Real) == 8;
+            int hsel = tid;
+            if constexpr (HALO_IN_STEP) asm volatile("" : "+v"(hsel));
+            const bool has_halo = hsel < TL::NHALO;
             if (has_halo) {
-                const int h = tid;
+                const int h = hsel;
                 if (h < 6 * BY) {
                     hj = h / 6;
                     const int k = h % 6;
