@@ -172,7 +172,6 @@ struct AdjointArgs {
     Material<double> mat;
     double weps;
     double idx, idy, idz;
-    double ih;  // 1/h of the direction being processed (set by the launcher)
 };
 // Ubar = (dR/dU)^T Rbar (overwritten), FP64
 hipError_t launch_rhs_adjoint(const AdjointArgs& a, const double* U, const double* Rbar, double* Ubar, hipStream_t st);
