@@ -207,22 +207,22 @@ __device__ __forceinline__ void prim_to_cons(const Material<Real>& mat, const Re
 // WENO-Z weights (q = 1) in FP32 for data of any magnitude: g_k = 1 + tau / e_k
 // (e_k = beta_k + eps) overflows once tau exceeds ~1e8 with eps = 1e-30 (a jump
 // of ~2e4 in the reconstructed variable, e.g. a pressure jump in pascals).  The
-// weights divided by the largest one, s_k = g_k / max g = A + C e_min / e_k with
+// weights divided by the largest one, s_k = g_k / max g = A + (e_min C) / e_k with
 // A = e_min / (e_min + tau) and C = tau / (e_min + tau) = 1 - A, normalise to the
 // same nonlinear weights, stay in [0, 1] and keep s = 1 for the smoothest
-// candidate when A underflows (tau / e_min beyond the FP32 range).  Weights of
-// order one also keep the weighted sums of small-valued fields out of the
-// denormal range, which weights scaled by e_min (>= eps) do not.  FP64
-// (eps = 1e-40) keeps the plain form.
+// candidate when A underflows (tau / e_min beyond the FP32 range; e_min C stays
+// near e_min >= eps).  Weights of order one also keep the weighted sums of
+// small-valued fields out of the denormal range, which weights scaled by e_min
+// do not.  FP64 (eps = 1e-40) keeps the plain form.
 __device__ __forceinline__ void weno_z_scaled(float tau, float e0, float e1, float e2, float& s0, float& s1,
                                               float& s2)
 {
     const float em = fminf(fminf(e0, e1), e2);
     const float inv = rcp(em + tau);
-    const float A = em * inv, C = tau * inv;
-    s0 = fmaf(C, em * rcp(e0), A);
-    s1 = fmaf(C, em * rcp(e1), A);
-    s2 = fmaf(C, em * rcp(e2), A);
+    const float A = em * inv, Cm = em * (tau * inv);
+    s0 = fmaf(Cm, rcp(e0), A);
+    s1 = fmaf(Cm, rcp(e1), A);
+    s2 = fmaf(Cm, rcp(e2), A);
 }
 
 template <typename Real>
@@ -415,11 +415,11 @@ __device__ __forceinline__ Real teno6a_one(Real a, Real b, Real c, Real d, Real 
         g3 = pow6(fma(Bn, r3, An));
     } else {
         const Real inv = rcp(em + tau);
-        const Real An = em * inv, Cn = tau * inv;
-        g0 = pow6(fma(Cn, em * r0, An));
-        g1 = pow6(fma(Cn, em * r1, An));
-        g2 = pow6(fma(Cn, em * r2, An));
-        g3 = pow6(fma(Cn, em * r3, An));
+        const Real An = em * inv, Cm = em * (tau * inv);
+        g0 = pow6(fma(Cm, r0, An));
+        g1 = pow6(fma(Cm, r1, An));
+        g2 = pow6(fma(Cm, r2, An));
+        g3 = pow6(fma(Cm, r3, An));
     }
     const Real thr = ct * (g0 + g1 + g2 + g3);
     const Real w0 = g0 >= thr ? Real(1) : Real(0), w1 = g1 >= thr ? Real(9) : Real(0);
