@@ -274,6 +274,15 @@ int adjoint_workspace_bytes(const fv_config* cfg, size_t* out);
  * coverage as rhs_adjoint. */
 int rk3_step_adjoint(const fv_config* cfg, const void* Un, void* Ubar, double dt, void* aws, void* stream);
 
+/* rk3_step_adjoint with the step's stage states given instead of recomputed
+ * (Sec. 3.4): U1 = U^(1) and U2 = U^(2) of the forward step from Un at the same
+ * dt, as rk3_stage writes them (stage 1 from Un, stage 2 from Un and U1), device
+ * arrays of the state layout, read only.  Ubar (in place, as for
+ * rk3_step_adjoint) must not overlap Un, U1 or U2.  aws: adjoint_workspace_bytes()
+ * of device memory.  Same coverage and errors as rk3_step_adjoint. */
+int rk3_step_adjoint_stages(const fv_config* cfg, const void* Un, const void* U1, const void* U2, void* Ubar,
+                            double dt, void* aws, void* stream);
+
 /* Scan U for NaN/Inf and for cells outside the admissible set of Sec. 3.3
  * (rho > 0 and rho c^2 > 0; DIM: 0 <= a1 <= 1, a_k rho_k > 0).  Synchronises
  * the stream.  Returns the status also stored in out->status. */

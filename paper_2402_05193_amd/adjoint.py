@@ -8,9 +8,10 @@ Sec. 3.2, and of the Runge-Kutta stages, Sec. 3.4), the derivative the paper
 obtains by automatic differentiation of its solver (Sec. 6).
 
 Memory: the forward pass keeps one state every ``every`` steps (checkpoints);
-the backward pass recomputes the states of one segment at a time from its
-checkpoint and sweeps it in reverse, so at most ``every`` + nsteps/every
-states are held.  The time step is a constant of the trajectory (not
+the backward pass recomputes one segment at a time from its checkpoint, stage by
+stage (``rk3_stage``), keeping every step's state and its two stage states, and
+sweeps it in reverse with ``rk3_step_adjoint_stages`` (the stage states are not
+recomputed), so at most 3 ``every`` + nsteps/every states are held.  The time step is a constant of the trajectory (not
 differentiated).  Coverage is that of rk3_step_adjoint: single-phase Euler,
 FP64, limiters off.
 
@@ -41,11 +42,12 @@ def _scratch(kind: str, nbytes: int, device) -> torch.Tensor:
 
 
 def _segment_states(every: int, like: torch.Tensor) -> torch.Tensor:
-    """Buffer for the recomputed states of one checkpoint segment (reused)."""
+    """Buffer for the recomputed states of one checkpoint segment (reused): for each
+    step its state U^n and its stage states U^(1), U^(2)."""
     key = ("segment", every, tuple(like.shape), like.dtype, str(like.device))
     t = _WS.get(key)
     if t is None:
-        t = torch.empty((every,) + tuple(like.shape), dtype=like.dtype, device=like.device)
+        t = torch.empty((every, 3) + tuple(like.shape), dtype=like.dtype, device=like.device)
         _WS[key] = t
     return t
 
@@ -69,20 +71,22 @@ class _Advance(torch.autograd.Function):
         cfg, nsteps, dt, every = ctx.cfg, ctx.nsteps, ctx.dt, ctx.every
         ckpts = ctx.saved_tensors
         G = Ubar.detach().clone().contiguous()
-        ws = _scratch("ws", S.workspace_bytes(cfg), G.device)
         aws = _scratch("aws", S.adjoint_workspace_bytes(cfg), G.device)
         states = _segment_states(every, G)
         for seg in range(len(ckpts) - 1, -1, -1):
             first = seg * every
             count = min(every, nsteps - first)
-            # states of the segment: the checkpoint, then each step recomputed in place
-            # from the previous one
-            states[0].copy_(ckpts[seg])
-            for n in range(1, count):
-                states[n].copy_(states[n - 1])
-                S.rk3_step(cfg, states[n], dt, ws)
+            # the segment recomputed stage by stage from its checkpoint (the same stage
+            # kernels as rk3_step): U^n, U^(1), U^(2) of every step
+            states[0, 0].copy_(ckpts[seg])
+            for n in range(count):
+                Un, U1, U2 = states[n, 0], states[n, 1], states[n, 2]
+                S.rk3_stage(cfg, 1, Un, Un, U1, dt)
+                S.rk3_stage(cfg, 2, Un, U1, U2, dt)
+                if n + 1 < count:
+                    S.rk3_stage(cfg, 3, Un, U2, states[n + 1, 0], dt)
             for n in range(count - 1, -1, -1):
-                S.rk3_step_adjoint(cfg, states[n], G, dt, aws)
+                S.rk3_step_adjoint_stages(cfg, states[n, 0], states[n, 1], states[n, 2], G, dt, aws)
         return G, None, None, None, None
 
 

@@ -713,6 +713,36 @@ int adjoint_workspace_bytes(const fv_config* cfg, size_t* out)
     return FV_OK;
 }
 
+}  // extern "C"
+
+// Reverse sweep of one TVD-RK3 step from its stage states U1, U2 (Sec. 3.4):
+// U1 = Un + dt R(Un); U2 = 3/4 Un + 1/4 U1 + 1/4 dt R(U1); U3 = 1/3 Un + 2/3 U2 + 2/3 dt R(U2).
+// On entry Ubar holds the cotangent of U3, on return that of Un.  aws holds G2, G1 and T
+// at state slots 2, 3 and 4 (slots 0 and 1 are free for the caller's stage states).
+static int step_adjoint_sweep(const fv_config* cfg, const void* Un, const void* U1p, const void* U2p, void* Ubar,
+                              double dt, void* aws, hipStream_t st)
+{
+    const size_t sb = (state_bytes(cfg) + 255) & ~(size_t)255;
+    const double* U1 = (const double*)U1p;
+    const double* U2 = (const double*)U2p;
+    double* G2 = (double*)((char*)aws + 2 * sb);
+    double* G1 = (double*)((char*)aws + 3 * sb);
+    double* T = (double*)((char*)aws + 4 * sb);
+    double* G3 = (double*)Ubar;
+    const long long n = 5ll * cfg->nx * cfg->ny * cfg->nz;
+    const fv::AdjointArgs a = adjoint_args(cfg);
+    hipError_t e = fv::launch_rhs_adjoint(a, U2, G3, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G2, n, 2.0 / 3.0, G3, 2.0 / 3.0 * dt, T, 0, nullptr, 0, nullptr, st);
+    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, U1, G2, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G1, n, 0.25, G2, 0.25 * dt, T, 0, nullptr, 0, nullptr, st);
+    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, (const double*)Un, G1, T, st);
+    if (e == hipSuccess) e = fv::launch_lincomb(G3, n, 1.0 / 3.0, G3, 0.75, G2, 1.0, G1, dt, T, st);
+    if (e != hipSuccess) return hip_fail(e, "rk3_step_adjoint");
+    return FV_OK;
+}
+
+extern "C" {
+
 int rk3_step_adjoint(const fv_config* cfg, const void* Un, void* Ubar, double dt, void* aws, void* stream)
 {
     int r = validate(cfg);
@@ -722,27 +752,26 @@ int rk3_step_adjoint(const fv_config* cfg, const void* Un, void* Ubar, double dt
     if (!(dt > 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and > 0");
     hipStream_t st = (hipStream_t)stream;
     const size_t sb = (state_bytes(cfg) + 255) & ~(size_t)255;
-    double* U1 = (double*)((char*)aws);
-    double* U2 = (double*)((char*)aws + sb);
-    double* G2 = (double*)((char*)aws + 2 * sb);
-    double* G1 = (double*)((char*)aws + 3 * sb);
-    double* T = (double*)((char*)aws + 4 * sb);
-    double* G3 = (double*)Ubar;
-    const long long n = 5ll * cfg->nx * cfg->ny * cfg->nz;
-    const fv::AdjointArgs a = adjoint_args(cfg);
+    void* U1 = aws;
+    void* U2 = (char*)aws + sb;
     // the stages of the forward step, recomputed from U^n
     if ((r = stage_dispatch(cfg, 1, Un, Un, U1, dt, nullptr, st))) return r;
     if ((r = stage_dispatch(cfg, 2, Un, U1, U2, dt, nullptr, st))) return r;
-    // reverse sweep of U1 = Un + dt R(Un); U2 = 3/4 Un + 1/4 U1 + 1/4 dt R(U1);
-    // U3 = 1/3 Un + 2/3 U2 + 2/3 dt R(U2)
-    hipError_t e = fv::launch_rhs_adjoint(a, U2, G3, T, st);
-    if (e == hipSuccess) e = fv::launch_lincomb(G2, n, 2.0 / 3.0, G3, 2.0 / 3.0 * dt, T, 0, nullptr, 0, nullptr, st);
-    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, U1, G2, T, st);
-    if (e == hipSuccess) e = fv::launch_lincomb(G1, n, 0.25, G2, 0.25 * dt, T, 0, nullptr, 0, nullptr, st);
-    if (e == hipSuccess) e = fv::launch_rhs_adjoint(a, (const double*)Un, G1, T, st);
-    if (e == hipSuccess) e = fv::launch_lincomb(G3, n, 1.0 / 3.0, G3, 0.75, G2, 1.0, G1, dt, T, st);
-    if (e != hipSuccess) return hip_fail(e, "rk3_step_adjoint");
-    return FV_OK;
+    return step_adjoint_sweep(cfg, Un, U1, U2, Ubar, dt, aws, st);
+}
+
+int rk3_step_adjoint_stages(const fv_config* cfg, const void* Un, const void* U1, const void* U2, void* Ubar,
+                            double dt, void* aws, void* stream)
+{
+    int r = validate(cfg);
+    if (r) return r;
+    if ((r = adjoint_supported(cfg))) return r;
+    if ((r = check_ptr(Un, "Un")) || (r = check_ptr(U1, "U1")) || (r = check_ptr(U2, "U2")) ||
+        (r = check_ptr(Ubar, "Ubar")) || (r = check_ptr(aws, "aws")))
+        return r;
+    if (Ubar == Un || Ubar == U1 || Ubar == U2) return fail(FV_EINVAL, "Ubar must not overlap Un, U1 or U2");
+    if (!(dt > 0) || !isfinite(dt)) return fail(FV_EINVAL, "dt must be finite and > 0");
+    return step_adjoint_sweep(cfg, Un, U1, U2, Ubar, dt, aws, (hipStream_t)stream);
 }
 
 int check_state(const fv_config* cfg, const void* U, void* ws, fv_report* out, void* stream)

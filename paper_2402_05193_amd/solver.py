@@ -28,7 +28,7 @@ LIB_PATH = os.environ.get("FVRK3_LIB", os.path.join(_HERE, "libfvrk3.so"))
 EXPORTED = ["fv_ncomp", "workspace_bytes", "init_state", "prim_to_cons", "cons_to_prim", "rhs", "rhs_ws",
             "limiter_flag_bytes", "rhs_flags", "rk3_stage",
             "rk3_stage3_cfl", "rk3_step", "compute_dt", "advance", "advance_noalloc", "rhs_adjoint", "adjoint_workspace_bytes",
-            "rk3_step_adjoint", "check_state", "workspace_time",
+            "rk3_step_adjoint", "rk3_step_adjoint_stages", "check_state", "workspace_time",
             "batch_table_bytes", "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_step_graph",
             "batch_graph_count", "stage_workgroups", "last_error"]
 
@@ -187,6 +187,7 @@ def _declare(L):
     L.rhs_adjoint.argtypes = [cp, vp, vp, vp, vp, vp]
     L.adjoint_workspace_bytes.argtypes = [cp, ctypes.POINTER(ctypes.c_size_t)]
     L.rk3_step_adjoint.argtypes = [cp, vp, vp, ctypes.c_double, vp, vp]
+    L.rk3_step_adjoint_stages.argtypes = [cp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.check_state.argtypes = [cp, vp, vp, ctypes.POINTER(Report), vp]
     L.workspace_time.argtypes = [cp, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.batch_table_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
@@ -416,6 +417,17 @@ def rk3_step_adjoint(cfg: Config, Un: torch.Tensor, Ubar: torch.Tensor, dt: floa
     _state(cfg, Ubar, "Ubar")
     c = cfg.c_struct()
     _check(lib().rk3_step_adjoint(ctypes.byref(c), _ptr(Un), _ptr(Ubar), float(dt), _ptr(aws), _stream(stream)))
+    return Ubar
+
+
+def rk3_step_adjoint_stages(cfg: Config, Un: torch.Tensor, U1: torch.Tensor, U2: torch.Tensor, Ubar: torch.Tensor,
+                            dt: float, aws: torch.Tensor, stream=None):
+    """rk3_step_adjoint with the step's stage states U1, U2 given (as rk3_stage computes them)."""
+    for t, n in ((Un, "Un"), (U1, "U1"), (U2, "U2"), (Ubar, "Ubar")):
+        _state(cfg, t, n)
+    c = cfg.c_struct()
+    _check(lib().rk3_step_adjoint_stages(ctypes.byref(c), _ptr(Un), _ptr(U1), _ptr(U2), _ptr(Ubar), float(dt),
+                                         _ptr(aws), _stream(stream)))
     return Ubar
 
 

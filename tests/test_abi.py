@@ -103,10 +103,14 @@ def test_stage_and_step_validation():
         cb = bad.c_struct()
         assert L.rhs_adjoint(ctypes.byref(cb), 256, 512, 768, None, None) == S.EUNSUPPORTED
         assert L.rk3_step_adjoint(ctypes.byref(cb), 256, 512, 1e-3, 768, None) == S.EUNSUPPORTED
+        assert L.rk3_step_adjoint_stages(ctypes.byref(cb), 256, 320, 384, 512, 1e-3, 768, None) == S.EUNSUPPORTED
     assert L.rhs_adjoint(ctypes.byref(c), 256, 512, 256, None, None) == S.EINVAL    # Ubar aliases U
     assert L.rhs_adjoint(ctypes.byref(c), 256, None, 768, None, None) == S.ENULL
     assert L.rk3_step_adjoint(ctypes.byref(c), 256, 512, 0.0, 768, None) == S.EINVAL  # dt <= 0
     assert L.rk3_step_adjoint(ctypes.byref(c), 256, 512, 1e-3, None, None) == S.ENULL
+    assert L.rk3_step_adjoint_stages(ctypes.byref(c), 256, None, 384, 512, 1e-3, 768, None) == S.ENULL  # U1
+    assert L.rk3_step_adjoint_stages(ctypes.byref(c), 256, 320, 384, 320, 1e-3, 768, None) == S.EINVAL  # Ubar = U1
+    assert L.rk3_step_adjoint_stages(ctypes.byref(c), 256, 320, 384, 512, 0.0, 768, None) == S.EINVAL  # dt <= 0
     assert L.init_state(ctypes.byref(c), 99, None, 0, 0, 256, None) == S.EINVAL
     p = (ctypes.c_double * 2)(0.1, 1.0)
     assert L.init_state(ctypes.byref(c), S.CASE_TGV, p, 2, 0, 256, None) == S.EINVAL  # too few params

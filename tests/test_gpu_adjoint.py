@@ -121,6 +121,33 @@ def test_rk3_step_adjoint_matches_oracle(name):
     assert r <= 1e-11
 
 
+@pytest.mark.parametrize("name", ["rough_periodic", "rough_mixed_bc", "turbulence_16"])
+def test_rk3_step_adjoint_stages_matches_recomputing_sweep(name):
+    """The sweep from given stage states (rk3_stage's U^(1), U^(2)) against the one
+    that recomputes them, and against the oracle's VJP: the same up to the order of
+    the atomic additions."""
+    oc, U, cfg = setup_named(name)
+    dt = 0.3 * O.compute_dt(oc, U, 1.0)
+    rng = np.random.default_rng(11)
+    G = rng.standard_normal(U.shape)
+    ref = ET.rk3_step_vjp(oc, torch.from_numpy(U), dt, torch.from_numpy(G)).numpy()
+    Ud = dev(U)
+    U1 = torch.empty_like(Ud)
+    U2 = torch.empty_like(Ud)
+    S.rk3_stage(cfg, 1, Ud, Ud, U1, dt)
+    S.rk3_stage(cfg, 2, Ud, U1, U2, dt)
+    aws = S.adjoint_workspace(cfg)
+    Ga = dev(G)
+    Gb = dev(G)
+    S.rk3_step_adjoint(cfg, Ud, Ga, dt, aws)
+    S.rk3_step_adjoint_stages(cfg, Ud, U1, U2, Gb, dt, aws)
+    a, b = Ga.cpu().numpy(), Gb.cpu().numpy()
+    r_ab, r_ref = rel(b, a), rel(b, ref)
+    print(f"{name}: rk3_step_adjoint_stages rel to recomputing sweep {r_ab:.3e}, to oracle {r_ref:.3e}", flush=True)
+    assert r_ab <= 1e-13
+    assert r_ref <= 1e-11
+
+
 def test_trajectory_gradient_matches_oracle_and_checkpointing():
     """d KE(U_N) / d U_0 over N = 7 fixed-dt steps (checkpoint segments 3, 3, 1)
     against torch.autograd through the oracle's steps; the checkpoint spacing
