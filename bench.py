@@ -17,6 +17,7 @@ view (algorithmic bytes over the same duration) is reported beside it.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import struct
 import json
@@ -67,12 +68,19 @@ def flops_per_cell(model: int, recon: int = 0, scheme: int = 0, visc_order: int 
     return weno + hllc + visc + conv + div + rk
 
 
-PROFILE_MD = os.path.join(ROOT, "profiles", "stage_kernel_ns_tgv256_f64.md")
+PROFILES_DIR = os.path.join(ROOT, "profiles")
 
 
 # the benchmarked instantiation: stage_kernel<double, NS, positivity off, primitive
 # reconstruction, constant viscosity, 16x16 tile, 256 threads>
 STAGE_KERNEL_SYMBOL = "_ZN2fv12stage_kernelIdLi1ELi0ELi0ELi0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE"
+# the stage instantiation each workload with committed counter records runs: the NS
+# default above, and the five-equation shock-bubble's <double, DIM, limiters on,
+# primitive reconstruction, no THINC, 16x16 tile, 256 threads>
+WORKLOAD_KERNELS = {
+    "ns-f64-256": STAGE_KERNEL_SYMBOL,
+    "dim-f64-256": "_ZN2fv12stage_kernelIdLi2ELi1ELi0ELi0ELi16ELi16ELi256EEEvNS_9StageArgsIT_EE",
+}
 
 
 def _elf_sections(elf: bytes):
@@ -131,17 +139,19 @@ def stage_kernel_hash(symbol: str = STAGE_KERNEL_SYMBOL) -> str:
 
 def _profile_record(kind: str, workload_key: str):
     """The numbers of a record line ('<kind>-record: kernel=<fingerprint> workload=<key>
-    name=value ...') of the committed rocprofv3 summary, if it was taken on the current
-    kernel (same fingerprint) and workload; else None."""
-    if not os.path.exists(PROFILE_MD):
+    name=value ...') of a committed rocprofv3 summary under profiles/, if it was taken on
+    the workload's current stage kernel (same fingerprint); else None."""
+    symbol = WORKLOAD_KERNELS.get(workload_key)
+    if symbol is None or not os.path.isdir(PROFILES_DIR):
         return None
-    want = stage_kernel_hash()
+    want = stage_kernel_hash(symbol)
     pat = re.compile(kind + r"-record: kernel=(\w+) workload=(\S+)((?: \w+=[\d.e+-]+)+)")
-    with open(PROFILE_MD) as fh:
-        for line in fh:
-            m = pat.search(line)
-            if m and m.group(1) == want and m.group(2) == workload_key:
-                return {k: float(v) for k, v in re.findall(r"(\w+)=([\d.e+-]+)", m.group(3))}
+    for path in sorted(glob.glob(os.path.join(PROFILES_DIR, "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                m = pat.search(line)
+                if m and m.group(1) == want and m.group(2) == workload_key:
+                    return {k: float(v) for k, v in re.findall(r"(\w+)=([\d.e+-]+)", m.group(3))}
     return None
 
 
@@ -534,8 +544,6 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * cbuf.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del cbuf, cdst
-    default_kernel = (model == S.NS and dtype == S.F64 and args.recon == 0 and args.scheme == 0
-                      and cfg.visc_order != 6)
     workload_key = (f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
                     + ("-teno" if args.scheme else "") + ("-v6" if cfg.visc_order == 6 else "")
                     + ("-thinc" if args.thinc else ""))
@@ -565,7 +573,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak, "traffic": traffic,
                      "kernel": "stage_kernel", "flops_per_cell": fpc,
-                     "kernel_fingerprint": stage_kernel_hash() if default_kernel else None,
+                     "kernel_fingerprint": (stage_kernel_hash(WORKLOAD_KERNELS[workload_key])
+                                            if workload_key in WORKLOAD_KERNELS else None),
                      # max(t_HBM, t_ALU) / t over the algorithmic bytes and operations: the
                      # fraction of the attainable roofline, and the resource that sets it
                      "attainable_frac": max(t_alu, t_hbm) / t_stage,

@@ -30,14 +30,20 @@ def test_bytes_per_cell():
 
 
 def test_traffic_record_needs_the_current_kernel(tmp_path, monkeypatch):
-    rec = tmp_path / "p.md"
-    rec.write_text("traffic-record: kernel=abc workload=ns-f64-256 fetch_bytes=10 write_bytes=5\n")
-    monkeypatch.setattr(bench, "PROFILE_MD", str(rec))
-    monkeypatch.setattr(bench, "stage_kernel_hash", lambda: "abc")
+    (tmp_path / "p.md").write_text("traffic-record: kernel=abc workload=ns-f64-256 fetch_bytes=10 write_bytes=5\n")
+    (tmp_path / "q.md").write_text("valu-record: kernel=xyz workload=dim-f64-256 insts_per_cell=7.5\n"
+                                   "traffic-record: kernel=xyz workload=dim-f64-256 fetch_bytes=3 write_bytes=4\n")
+    monkeypatch.setattr(bench, "PROFILES_DIR", str(tmp_path))
+    # each workload's record is matched against its own stage kernel's fingerprint
+    fps = {bench.WORKLOAD_KERNELS["ns-f64-256"]: "abc", bench.WORKLOAD_KERNELS["dim-f64-256"]: "xyz"}
+    monkeypatch.setattr(bench, "stage_kernel_hash", lambda symbol=bench.STAGE_KERNEL_SYMBOL: fps[symbol])
     assert bench.measured_traffic("ns-f64-256") == 15
-    assert bench.measured_traffic("ns-f32-256") is None
-    monkeypatch.setattr(bench, "stage_kernel_hash", lambda: "def")
+    assert bench.measured_traffic("dim-f64-256") == 7
+    assert bench.measured_valu_insts_per_cell("dim-f64-256") == 7.5
+    assert bench.measured_traffic("ns-f32-256") is None     # no kernel known for the workload
+    fps[bench.WORKLOAD_KERNELS["ns-f64-256"]] = "def"       # the kernel changed since the record
     assert bench.measured_traffic("ns-f64-256") is None
+    assert bench.measured_traffic("dim-f64-256") == 7
 
 
 def test_more_than_one_gpu_is_refused():
