@@ -547,8 +547,16 @@ def main():
     workload_key = (f"{args.model}-{args.dtype}-{args.n}" + ("-char" if args.recon else "")
                     + ("-teno" if args.scheme else "") + ("-v6" if cfg.visc_order == 6 else "")
                     + ("-thinc" if args.thinc else ""))
-    traffic = measured_traffic(workload_key)
-    valu_per_cell = measured_valu_insts_per_cell(workload_key)
+    # the stage instantiation this configuration runs, where it is one of the two profiled ones
+    # (NS with the limiters off, the five-equation model with them on: positivity -1 selects
+    # on for that model only); its fingerprint does not depend on the grid
+    limiters_on = cfg.positivity == 1 or (cfg.positivity < 0 and model == S.DIM)
+    kernel_symbol = None
+    if workload_key.count("-") == 2 and limiters_on == (model == S.DIM):
+        kernel_symbol = {"ns-f64": WORKLOAD_KERNELS["ns-f64-256"],
+                         "dim-f64": WORKLOAD_KERNELS["dim-f64-256"]}.get(workload_key.rsplit("-", 1)[0])
+    traffic = measured_traffic(workload_key) if kernel_symbol else None
+    valu_per_cell = measured_valu_insts_per_cell(workload_key) if kernel_symbol else None
     t_stage = mean_stage_ms * 1e-3
     t_alu = flops_launch / (peak * 1e12)
     t_hbm = alg_bytes / (PEAK_HBM_GBS * 1e9)
@@ -573,8 +581,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak, "traffic": traffic,
                      "kernel": "stage_kernel", "flops_per_cell": fpc,
-                     "kernel_fingerprint": (stage_kernel_hash(WORKLOAD_KERNELS[workload_key])
-                                            if workload_key in WORKLOAD_KERNELS else None),
+                     "kernel_fingerprint": stage_kernel_hash(kernel_symbol) if kernel_symbol else None,
                      # max(t_HBM, t_ALU) / t over the algorithmic bytes and operations: the
                      # fraction of the attainable roofline, and the resource that sets it
                      "attainable_frac": max(t_alu, t_hbm) / t_stage,
