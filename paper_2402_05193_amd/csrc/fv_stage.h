@@ -503,7 +503,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<Real>& a, const int b
             // halo cell is converted and staged at once instead of being held through the
             // ring's psi (the compiler otherwise spilled its loads one by one as they arrived):
             // 1.297 -> 1.266 ms per stage for the five-equation THINC shock-bubble at
-            // 256x128x128; characteristic TENO6-A with THINC measured 0.7 % slower so
+            // 256x128x128; with THINC the other reconstruction families measured equal or
+            // 0.7-1.3 % slower so
             constexpr bool HALO_EARLY = THINC && sizeof(Real) == 8 && REC == REC_WENO_PRIM;
             bool halo_done = false;  // uniform: the previous step had x/y phases
             if constexpr (HALO_EARLY) {
