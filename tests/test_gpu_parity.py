@@ -406,14 +406,17 @@ def test_fp32_trajectory_error_statement():
 
 FULL_OPTS = {
     "": {},
+    "char": dict(recon=1),
     "teno": dict(scheme=1),
     "single_phase_setup": dict(scheme=1, visc_order=6),    # TENO6-A + sixth-order viscous fluxes
+    "thinc": dict(thinc=1),
     "char_teno_thinc": dict(scheme=1, recon=1, thinc=1),
 }
 
 
-@pytest.mark.parametrize("cfgname,opt", [("ns_tgv_256", ""), ("dim_sbi_256x128x128", ""), ("ns_tgv_256", "teno"),
-                                         ("ns_tgv_256", "single_phase_setup"),
+@pytest.mark.parametrize("cfgname,opt", [("ns_tgv_256", ""), ("dim_sbi_256x128x128", ""), ("ns_tgv_256", "char"),
+                                         ("ns_tgv_256", "teno"), ("ns_tgv_256", "single_phase_setup"),
+                                         ("dim_sbi_256x128x128", "thinc"),
                                          ("dim_sbi_256x128x128", "char_teno_thinc")])
 def test_full_size_sampled_parity(cfgname, opt):
     """The benchmark's full-size workloads (and their f3/f4 variants) in the
