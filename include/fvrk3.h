@@ -174,9 +174,11 @@ int rhs(const fv_config* cfg, const void* U, void* R, double dt, void* stream);
  * otherwise the same as rhs).  The workspace contents are overwritten. */
 int rhs_ws(const fv_config* cfg, const void* U, void* R, double dt, void* ws, void* stream);
 
-/* Workgroups of one fused stage launch of the problem (alone, or its share of a
- * batched launch); a measure of how much of the GPU the problem fills (each
- * CU holds two FP64 or three FP32 stage workgroups at a time). */
+/* Workgroups of the problem's share of a batched stage launch; a measure of how
+ * much of the GPU the problem fills (each CU holds two FP64 or three FP32 stage
+ * workgroups at a time).  A single-problem launch has as many, except that the
+ * five-equation model may take fewer, longer z chunks alone when they still give
+ * every CU its full share. */
 int stage_workgroups(const fv_config* cfg, int32_t* out);
 
 /* Bytes of the limiter decision record of rhs_flags: one byte per cell face,

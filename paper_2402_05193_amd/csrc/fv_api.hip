@@ -64,9 +64,11 @@ size_t state_bytes(const fv_config* c)
 #ifndef FV_SMALLEST_ZCHUNK
 #define FV_SMALLEST_ZCHUNK 4
 #endif
-// Five-equation model: chunks lengthened (never shortened) up to FV_DIM_MAX_ZCHUNK planes
-// while the launch still gives every resident workgroup slot a workgroup (one round),
-// which saves repeated march starts.  Measured at 256x128x128 (ms per stage): FP64 with
+// Five-equation model, single-problem launches: chunks lengthened (never shortened) up to
+// FV_DIM_MAX_ZCHUNK planes while the launch still gives every resident workgroup slot a
+// workgroup (one round), which saves repeated march starts.  Batched members keep the
+// base chunks: with the lengthening the batched serving stream measured 1.5 % lower
+// throughput (40.2 against 40.8 requests/s), one-at-a-time solves equal.  Measured at 256x128x128 (ms per stage): FP64 with
 // 32-plane chunks (512 workgroups) 0.834 -> 0.814, characteristic 0.981 -> 0.964,
 // TENO6-A 1.417 -> 1.407, THINC 1.268 -> 1.244; FP32 with 22-plane chunks (768) 0.496 ->
 // 0.482, THINC 0.575 -> 0.562.  (NS 256^3 FP64 measured slower with longer chunks.)
@@ -195,8 +197,10 @@ bool positivity_on(const fv_config* c)
     return c->positivity < 0 ? c->model == FV_DIM : c->positivity == 1;
 }
 
+// solo: a single-problem launch (the five-equation chunk lengthening below applies;
+// batched members keep the base chunks, which interleave better with the other members)
 template <typename Real>
-fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
+fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g, bool solo = false)
 {
     fv::StageArgs<Real> a;
     memset(&a, 0, sizeof a);
@@ -219,7 +223,7 @@ fv::StageArgs<Real> stage_args(const fv_config* c, fv::LaunchGeom& g)
         const long long slots = (long long)RESIDENT_CUS * (f64 ? 2 : 3);
         while (zc / 2 >= FV_SMALLEST_ZCHUNK && tiles * ((c->nz + zc - 1) / zc) < slots) zc /= 2;
     }
-    if (c->model == FV_DIM) {
+    if (solo && c->model == FV_DIM) {
         const long long slots = (long long)RESIDENT_CUS * (f64 ? 2 : 3);
         const long long round_chunks = (slots + tiles - 1) / tiles;
         int zl = (int)((c->nz + round_chunks - 1) / round_chunks);
@@ -306,7 +310,7 @@ int stage_impl(const fv_config* c, int mode, const void* Un, const void* Uk, voi
                hipStream_t st, unsigned long long* inv_max, const WsLayout* w, unsigned char* flags = nullptr)
 {
     fv::LaunchGeom g;
-    fv::StageArgs<Real> a = stage_args<Real>(c, g);
+    fv::StageArgs<Real> a = stage_args<Real>(c, g, true);
     if (flags) {
         long long total;
         flag_offsets(c, a.flag_off, &total);
